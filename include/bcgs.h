@@ -1,0 +1,146 @@
+/*
+ * bcgs.h -- C ABI of the MI355X (gfx950) block classical Gram-Schmidt QR
+ * library.
+ *
+ * Computes the economic QR factorization X = Q R of a tall-skinny matrix
+ * (section 1 of Carson & Ma, "The Performance of Low-Synchronization
+ * Variants of Reorthogonalized Block Classical Gram-Schmidt", arXiv
+ * 2507.21791): X is m x n with m >= n, Q is m x n with orthonormal columns,
+ * R is n x n upper triangular with a positive diagonal.  The n columns are
+ * split into q = n / s block columns of width s (section 1), which are
+ * orthogonalized one after another by one of the variants of section 2.
+ *
+ * Conventions shared by every entry point
+ *   - Matrices are column-major.  X, Q are addressed by (pointer, leading
+ *     dimension); block column k (0-based) starts at column k*s.
+ *   - Pointers are DEVICE pointers unless the parameter says "host".
+ *   - All work is enqueued on the given HIP stream; calls return after
+ *     enqueueing (asynchronous), except argument errors, which are reported
+ *     synchronously before anything is enqueued.
+ *   - Numerical breakdown (a non-positive or non-finite pivot in one of the
+ *     Cholesky factorizations of Alg. 1 / Alg. 2) is not an error return:
+ *     the device writes it to a bcgs_info record, lets NaN propagate into
+ *     Q and R, and keeps going; read the record after the stream has
+ *     synchronized (bcgs_get_info, or the caller's own d_info).
+ *   - No call throws, exits or aborts.  The library is thread-safe for
+ *     calls on different streams.
+ */
+#ifndef BCGS_H
+#define BCGS_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* The variants compared in the paper (section 2; Table 1 lists their
+ * synchronization counts and stability assumptions). */
+typedef enum {
+    /* BCGSI+: BCGS applied twice per block column, TSQR for both
+     * intra-orthogonalizations; 4 synchronizations per block column
+     * (section 1; Table 1). */
+    BCGS_I_PLUS = 0,
+    /* BCGSI+P-2S: Alg. 2 with TSQR as the first intra-orthogonalization;
+     * 2 synchronizations per block column (section 2.3). */
+    BCGS_P_2S = 1,
+    /* BCGSI+P-1S: Alg. 2, one synchronization per block column, Pythagorean
+     * Cholesky for both intra-orthogonalizations and delayed normalization
+     * through eq. (1) (section 2.2). */
+    BCGS_P_1S = 2
+} bcgs_variant;
+
+/* Arithmetic of the streamed m-row data.  BCGS_FP64: everything in binary64.
+ * BCGS_FP32_BULK: X and Q are binary32 in memory and the per-row products are
+ * accumulated in binary32; the cross-row reductions, the s x s Gram and
+ * Cholesky work, the Pythagorean subtraction and R stay binary64. */
+typedef enum { BCGS_FP64 = 0, BCGS_FP32_BULK = 1 } bcgs_precision;
+
+typedef enum {
+    BCGS_OK = 0,
+    BCGS_ERR_ARG = 1,          /* invalid argument; nothing was enqueued */
+    BCGS_ERR_BREAKDOWN = 2,    /* Cholesky breakdown (only in bcgs_info) */
+    BCGS_ERR_NOMEM = 3,        /* device allocation failed */
+    BCGS_ERR_HIP = 4,          /* a HIP runtime call failed */
+    BCGS_ERR_QUEUE_FULL = 5,   /* request queue cannot admit more work */
+    BCGS_PENDING = 6,          /* request not finished yet */
+    BCGS_ERR_UNSUPPORTED = 7   /* valid but not supported in this build */
+} bcgs_status;
+
+/* Device-resident outcome of one factorization.
+ *   status  BCGS_OK or BCGS_ERR_BREAKDOWN
+ *   block   0-based block column whose Cholesky factor broke down (first one)
+ *   pivot   0-based pivot index inside that s x s factorization
+ *   stage   0: the first intra-orthogonalization (S_{k,k}),
+ *           1: the second one (Y_{k,k}), of Alg. 2
+ *   syncs   number of device-wide reductions the factorization performed
+ *   value   the offending pivot value */
+typedef struct {
+    int32_t status;
+    int32_t block;
+    int32_t pivot;
+    int32_t stage;
+    int32_t syncs;
+    int32_t reserved;
+    double value;
+} bcgs_info;
+
+/* X = Q R with library-owned workspace and info (section 1).
+ *   X  m x n, leading dimension m, binary64, read only (never written)
+ *   Q  m x n output, leading dimension m; must not overlap X
+ *   R  n x n output, leading dimension n; the strictly lower part is set to 0
+ *   s  block width: 1 <= s <= 64 and s divides n; m >= n
+ * The library keeps one workspace per stream (grown on demand, freed by
+ * bcgs_release) and one info record per stream (bcgs_get_info).  Returns
+ * BCGS_ERR_ARG on invalid arguments, BCGS_ERR_NOMEM / BCGS_ERR_HIP when the
+ * workspace cannot be set up, BCGS_OK otherwise. */
+bcgs_status bcgs_qr(const double* X, int64_t m, int64_t n, int64_t s,
+                    bcgs_variant variant, double* Q, double* R,
+                    hipStream_t stream);
+
+/* General form of bcgs_qr: leading dimensions, precision, caller-provided
+ * workspace and info.
+ *   X, Q     binary64 (BCGS_FP64) or binary32 (BCGS_FP32_BULK) elements
+ *   ldx, ldq >= m
+ *   R        always binary64, ldr >= n
+ *   workspace, ws_bytes  device buffer of at least bcgs_workspace_size()
+ *            bytes, 256-byte aligned, used exclusively by this call until
+ *            the stream reaches its end
+ *   d_info   device pointer to one bcgs_info, written by the call */
+bcgs_status bcgs_qr_ex(const void* X, int64_t ldx, int64_t m, int64_t n,
+                       int64_t s, bcgs_variant variant,
+                       bcgs_precision precision, void* Q, int64_t ldq,
+                       double* R, int64_t ldr, void* workspace,
+                       size_t ws_bytes, bcgs_info* d_info,
+                       hipStream_t stream);
+
+/* Bytes of device workspace bcgs_qr_ex needs for this problem (0 on invalid
+ * arguments).  No device call is made. */
+size_t bcgs_workspace_size(int64_t m, int64_t n, int64_t s,
+                           bcgs_variant variant, bcgs_precision precision);
+
+/* Number of device-wide reductions ("synchronization points", section 1)
+ * the factorization of an m x n matrix with block width s performs:
+ * q + 1 for BCGSI+P-1S, 2q for BCGSI+P-2S, 4q - 3 for BCGSI+ (Table 1 gives
+ * the per-block-column rates q, 2q, 4q).  -1 on invalid arguments. */
+int32_t bcgs_sync_count(int64_t m, int64_t n, int64_t s,
+                        bcgs_variant variant);
+
+/* Waits for `stream` and copies the info record of the last bcgs_qr call on
+ * that stream into *host_out (host pointer).  BCGS_ERR_ARG if no bcgs_qr
+ * ran on the stream. */
+bcgs_status bcgs_get_info(hipStream_t stream, bcgs_info* host_out);
+
+/* Frees the library-owned workspaces of every stream (waits for them). */
+void bcgs_release(void);
+
+/* Human-readable name of a status code (static string). */
+const char* bcgs_status_string(bcgs_status status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BCGS_H */

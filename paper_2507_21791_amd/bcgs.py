@@ -1,0 +1,180 @@
+"""Python binding of the C ABI in include/bcgs.h (argument marshalling only).
+
+Every step of the factorization runs in the gfx950 library
+``_lib/libbcgs.so``; PyTorch supplies device memory and the stream.  If the
+library is missing this module raises: there is no fallback path.
+
+Matrices are torch tensors in column-major order: shape (m, n) with
+strides (1, ld) -- e.g. ``torch.empty(n, m).t()``.
+"""
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "_lib", "libbcgs.so")
+
+VARIANTS = {"bcgsi+": 0, "p-2s": 1, "p-1s": 2}
+PRECISIONS = {"fp64": 0, "fp32-bulk": 1}
+STATUS = {0: "ok", 1: "invalid argument", 2: "Cholesky breakdown",
+          3: "out of device memory", 4: "HIP runtime error", 5: "queue full",
+          6: "pending", 7: "unsupported"}
+BCGS_OK, BCGS_ERR_ARG, BCGS_ERR_BREAKDOWN = 0, 1, 2
+
+
+class Info(ctypes.Structure):
+    """Mirror of bcgs_info."""
+    _fields_ = [("status", ctypes.c_int32), ("block", ctypes.c_int32),
+                ("pivot", ctypes.c_int32), ("stage", ctypes.c_int32),
+                ("syncs", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("value", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
+INFO_BYTES = ctypes.sizeof(Info)
+_lib = None
+
+_PROTOS = {
+    "bcgs_qr": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64,
+                               ctypes.c_int64, ctypes.c_int64, ctypes.c_int,
+                               ctypes.c_void_p, ctypes.c_void_p,
+                               ctypes.c_void_p]),
+    "bcgs_qr_ex": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64,
+                                  ctypes.c_int64, ctypes.c_int64,
+                                  ctypes.c_int64, ctypes.c_int, ctypes.c_int,
+                                  ctypes.c_void_p, ctypes.c_int64,
+                                  ctypes.c_void_p, ctypes.c_int64,
+                                  ctypes.c_void_p, ctypes.c_size_t,
+                                  ctypes.c_void_p, ctypes.c_void_p]),
+    "bcgs_workspace_size": (ctypes.c_size_t, [ctypes.c_int64, ctypes.c_int64,
+                                              ctypes.c_int64, ctypes.c_int,
+                                              ctypes.c_int]),
+    "bcgs_sync_count": (ctypes.c_int32, [ctypes.c_int64, ctypes.c_int64,
+                                         ctypes.c_int64, ctypes.c_int]),
+    "bcgs_get_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Info)]),
+    "bcgs_release": (None, []),
+    "bcgs_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+}
+
+
+def lib():
+    """The loaded library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(
+                f"{LIB_PATH} is missing: build it with "
+                "`python -m paper_2507_21791_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _PROTOS.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+class BcgsError(RuntimeError):
+    def __init__(self, status, what=""):
+        super().__init__(f"{what}: {STATUS.get(status, status)}")
+        self.status = status
+
+
+def _stream_handle(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _col_major(t, name):
+    if t.dim() != 2 or t.stride(0) != 1 or t.stride(1) < max(1, t.shape[0]):
+        raise ValueError(f"{name} must be a column-major (m, n) tensor with "
+                         f"strides (1, ld >= m); got strides {t.stride()}")
+    return t.stride(1)
+
+
+def workspace_size(m, n, s, variant="p-1s", precision="fp64"):
+    return lib().bcgs_workspace_size(m, n, s, VARIANTS[variant],
+                                     PRECISIONS[precision])
+
+
+def sync_count(m, n, s, variant):
+    return lib().bcgs_sync_count(m, n, s, VARIANTS[variant])
+
+
+def empty_fortran(m, n, dtype, device):
+    import torch
+    return torch.empty((n, m), dtype=dtype, device=device).t()
+
+
+class Workspace:
+    """Device workspace + info record for repeated factorizations."""
+
+    def __init__(self, m, n, s, variant="p-1s", precision="fp64",
+                 device="cuda"):
+        import torch
+        nbytes = workspace_size(m, n, s, variant, precision)
+        if nbytes == 0:
+            raise BcgsError(BCGS_ERR_ARG, "workspace_size")
+        self.nbytes = nbytes
+        self.buf = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+        off = (-self.buf.data_ptr()) % 256
+        self.ptr = self.buf.data_ptr() + off
+        self.info_buf = torch.zeros(64, dtype=torch.uint8, device=device)
+
+    def info(self):
+        """Copy the info record to the host (synchronizes on the copy)."""
+        raw = self.info_buf[:INFO_BYTES].cpu().numpy().tobytes()
+        return Info.from_buffer_copy(raw)
+
+
+def qr(X, s, variant="p-1s", precision="fp64", Q=None, R=None, ws=None,
+       stream=None):
+    """Enqueue X = Q R on the current stream; returns (Q, R, ws).
+
+    ``ws.info()`` reads the breakdown record after the work has finished."""
+    import torch
+    m, n = X.shape
+    ldx = _col_major(X, "X")
+    want = torch.float64 if precision == "fp64" else torch.float32
+    if X.dtype != want:
+        raise ValueError(f"X must be {want} for precision {precision}")
+    if Q is None:
+        Q = empty_fortran(m, n, want, X.device)
+    ldq = _col_major(Q, "Q")
+    if R is None:
+        R = empty_fortran(n, n, torch.float64, X.device)
+    ldr = _col_major(R, "R")
+    if ws is None:
+        ws = Workspace(m, n, s, variant, precision, X.device)
+    st = lib().bcgs_qr_ex(
+        ctypes.c_void_p(X.data_ptr()), ldx, m, n, s, VARIANTS[variant],
+        PRECISIONS[precision], ctypes.c_void_p(Q.data_ptr()), ldq,
+        ctypes.c_void_p(R.data_ptr()), ldr, ctypes.c_void_p(ws.ptr),
+        ws.nbytes, ctypes.c_void_p(ws.info_buf.data_ptr()),
+        _stream_handle(stream))
+    if st != BCGS_OK:
+        raise BcgsError(st, "bcgs_qr_ex")
+    return Q, R, ws
+
+
+def qr_simple(X, s, variant, Q, R, stream=None):
+    """The library-owned-workspace entry point bcgs_qr (ld = m, n)."""
+    m, n = X.shape
+    st = lib().bcgs_qr(ctypes.c_void_p(X.data_ptr()), m, n, s,
+                       VARIANTS[variant], ctypes.c_void_p(Q.data_ptr()),
+                       ctypes.c_void_p(R.data_ptr()), _stream_handle(stream))
+    if st != BCGS_OK:
+        raise BcgsError(st, "bcgs_qr")
+    return Q, R
+
+
+def get_info(stream=None):
+    info = Info()
+    st = lib().bcgs_get_info(_stream_handle(stream), ctypes.byref(info))
+    if st != BCGS_OK:
+        raise BcgsError(st, "bcgs_get_info")
+    return info

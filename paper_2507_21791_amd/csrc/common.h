@@ -1,0 +1,147 @@
+// Internal declarations shared by the gfx950 kernels and the host driver.
+//
+// Data layout in HBM
+//   X, Q      column-major, block column k = columns [k*s, (k+1)*s).
+//   Q slot k  also holds the intermediate blocks of block column k before Q_k
+//             exists (U_k, V_k, W_k of section 2): every kernel that turns one
+//             into the next reads a row and writes the same row, so the
+//             update happens in place and no m-row scratch is needed.
+//   workspace small s x s / (n x s) coefficient matrices, the per-workgroup
+//             partial Gram matrices of the current reduction, and the TSQR
+//             tree (leaf R factors, node Q factors, downward coefficients).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/bcgs.h"
+
+namespace bcgs {
+
+constexpr int kMaxS = 64;          // largest block width
+constexpr int kThreads = 256;      // threads per workgroup of every kernel
+constexpr int kWaves = kThreads / 64;
+
+inline int round_up(int x, int m) { return (x + m - 1) / m * m; }
+inline int64_t round_up64(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
+inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// ---------------------------------------------------------------- pass ---
+// One streaming pass over the rows of the tall matrices: the only kind of
+// kernel that touches m-row data besides TSQR.  A workgroup owns a
+// contiguous range of rows and walks it in tiles of TR rows.  For each tile
+// it stages a window of columns in LDS (Q columns [0, nq), then an optional
+// block F, then an optional block E), optionally rewrites two blocks in
+// place through the block update of Alg. 1 / Alg. 2,
+//     B <- (B - Q_{1:j} C) T^{-1}      (T upper triangular, optional),
+// writes them back, and accumulates A^T B Gram products of LDS columns in
+// registers; at the end each workgroup writes its partial Gram matrix.
+template <typename T>
+struct PassArgs {
+  int64_t m;
+  int s;          // block width
+  int sp;         // s rounded up to 16 (MFMA tile width)
+  int tr;         // rows per tile: 16, 32 or 64
+  int64_t rows_per_wg;
+  int ncols;      // staged columns = nq + fcols + ecols
+  int ncols_p;    // ncols rounded up to 16 (extra columns are zero)
+  // sources of the staged columns
+  const T* q; int64_t ldq; int nq;
+  const T* f; int64_t ldf; int fcols;
+  const T* e; int64_t lde; int ecols;
+  // update 1: columns [u1_c0, u1_c0 + s) <- (cols - cols[0,u1_c0) C1) T1^-1
+  int upd1; int u1_c0;
+  const double* c1; const double* t1; T* dst1; int64_t ldd1;
+  // update 2: columns [u2_c0, u2_c0 + s) <- (cols - cols[0,u2_c0) C2) [T2^-1]
+  int upd2; int u2_c0; int trsm2;
+  const double* c2; const double* t2; T* dst2; int64_t ldd2;
+  // Gram: A = cols [0, ga), B = cols [gb0, gb0 + gbn)
+  int gram; int ga_p; int gb0; int gbn_p;
+  int a_blocks_per_group;  // 16-column A blocks handled by one y-group
+  int skip_a0;             // skip tiles with a >= skip_a0 and b < skip_b1
+  int skip_b1;
+  int groups;              // H: workgroups per row range (Gram split)
+  double* partial;         // [G][gbn_p][ga_p]
+};
+
+// coefficient matrices are stored row-major with row stride `sp` and zero
+// padding: C (K x s) at C[k * sp + j]; triangular T (s x s) the same.
+
+// ---------------------------------------------------------------- TSQR ---
+struct TsqrPlan {
+  int s;
+  int cr;          // rows per leaf chunk
+  int fan;         // children per tree node (fan * s <= cr)
+  int64_t nchunks;
+  int levels;      // upward tree levels (>= 1)
+  int64_t nodes[24];         // nodes[0] = nchunks, nodes[levels] = 1
+  int64_t r_off[24];         // offset (doubles) of level-l R factors
+  int64_t q_off[24];         // offset of level-l node Q factors (l >= 1)
+  int64_t c_off[24];         // offset of level-l downward coefficients
+  int64_t total;             // doubles
+};
+
+TsqrPlan make_tsqr_plan(int64_t m, int s);
+
+// ------------------------------------------------------- workspace plan ---
+struct Plan {
+  int64_t m, n;
+  int s, sp, q;
+  int variant, precision;
+  int G;                  // workgroups (row ranges) of the streaming passes
+  int64_t rows_per_wg;
+  int tr_max;             // largest tile the widest pass can afford
+  TsqrPlan tsqr;
+  // workspace offsets in bytes
+  size_t off_c1, off_c2, off_t1, off_t2, off_gram, off_partial, off_tsqr;
+  size_t off_scratch_info;
+  size_t bytes;
+  int64_t gram_ld;        // leading dimension of the reduced Gram matrix
+  int64_t partial_elems;  // per workgroup
+};
+
+bool make_plan(int64_t m, int64_t n, int64_t s, int variant, int precision,
+               Plan* p);
+
+// Launchers (return hipError_t of the launch).
+template <typename T>
+hipError_t launch_pass(const PassArgs<T>& a, int G, hipStream_t st);
+hipError_t launch_gram_reduce(const double* partial, int G, int64_t elems,
+                              double* out, hipStream_t st);
+
+struct EpiArgs;
+hipError_t launch_epilogue(const EpiArgs& a, hipStream_t st);
+
+// TSQR of the m x s block v (leading dimension ldv) into dst (may equal v);
+// the s x s factor R (positive diagonal) goes to r_out(i, j) =
+// r_out[i * r_rs + j * r_cs] (full square, zeros below the diagonal).
+template <typename T>
+hipError_t launch_tsqr(const TsqrPlan& tp, const T* v, int64_t ldv, T* dst,
+                       int64_t ldd, int64_t m, double* ws, double* r_out,
+                       int64_t r_rs, int64_t r_cs, hipStream_t st);
+
+hipError_t launch_fill(double* p, int64_t rows, int64_t cols, int64_t ld,
+                       double value, hipStream_t st);
+
+// --------------------------------------------------------- epilogues ---
+enum EpiMode : int {
+  EPI_S_ONLY = 0,     // C2 <- gram(0:js, 0:s)                      (S)
+  EPI_Y_ONLY = 1,     // C1 <- gram(0:js, 0:s)                      (Y)
+  EPI_P1S_INIT = 2,   // [S_12; T_2]: C2 <- S_12, T2 <- chol(T_2 - S^T S)
+  EPI_ONE_SYNC = 3,   // after [Q U]^T [U E]: Y_kk, R block column, eq. (1)
+  EPI_R_ASSEMBLE = 4, // BCGSI+: R block column from C2, C1, T2, T1
+};
+
+struct EpiArgs {
+  int mode;
+  int s, sp;
+  int j;              // block column index being completed (0-based)
+  int has_e;          // the Gram included E = X_{j+1}
+  int chol_s;         // form T2 <- chol(T - S^T S) (P-1S) after eq. (1)
+  const double* gram; int64_t gld;
+  double* c1; double* c2; double* t1; double* t2;
+  double* r; int64_t ldr;
+  bcgs_info* info;
+};
+
+}  // namespace bcgs

@@ -1,0 +1,436 @@
+// Host side: argument checks, workspace plan, the per-variant schedule of
+// streaming passes / reductions / epilogues, and the C ABI of bcgs.h.
+//
+// Schedules (0-based block columns j; B = one m x s block):
+//   BCGSI+ (section 1, Table 1; four reductions per block column)
+//     TSQR(X_0) -> Q_0, R_00
+//     for j = 1..q-1:
+//       S   = Q_{0:j-1}^T X_j                      pass + reduce
+//       V   = X_j - Q S -> slot j; TSQR(V) -> U_j, S_jj
+//       Y   = Q^T U_j                              pass + reduce
+//       W   = U_j - Q Y -> slot j; TSQR(W) -> Q_j, Y_jj
+//       R column block j from S, Y, S_jj, Y_jj
+//   BCGSI+P-1S (Alg. 2; one reduction per block column)
+//     TSQR(X_0); [S_01; T_1] = [Q_0 X_1]^T X_1; S_11 = chol(T_1 - S^T S)
+//     for j = 1..q-1: one pass that forms Q_{j-1} from U_{j-1} (j >= 2),
+//       forms U_j from X_j, and accumulates [Q_{0:j-1} U_j]^T [U_j X_{j+1}]
+//       and X_{j+1}^T X_{j+1}; then the epilogue (Y_jj, R, eq. (1), S_{j+1})
+//     last pass forms Q_{q-1}
+//   BCGSI+P-2S (section 2.3; two reductions per block column)
+//     as P-1S, but V_j = X_j - Q S is written and factored by TSQR, and
+//     the Gram pass runs after it; S_01 = Q_0^T X_1 is its own reduction.
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <algorithm>
+#include <map>
+#include <mutex>
+
+#include "common.h"
+
+namespace bcgs {
+
+template <typename T>
+size_t pass_lds_bytes(const PassArgs<T>& a);
+
+static bool valid_args(int64_t m, int64_t n, int64_t s, int variant,
+                       int precision) {
+  if (s < 1 || s > kMaxS || n < 1 || m < n || n % s != 0) return false;
+  if (variant < BCGS_I_PLUS || variant > BCGS_P_1S) return false;
+  if (precision != BCGS_FP64 && precision != BCGS_FP32_BULK) return false;
+  if (m > (int64_t(1) << 40)) return false;
+  return true;
+}
+
+static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+bool make_plan(int64_t m, int64_t n, int64_t s, int variant, int precision,
+               Plan* p) {
+  if (!valid_args(m, n, s, variant, precision)) return false;
+  Plan P{};
+  P.m = m; P.n = n; P.s = (int)s; P.sp = round_up((int)s, 16);
+  P.q = (int)(n / s);
+  P.variant = variant; P.precision = precision;
+  const int64_t target_wg = 512;
+  P.rows_per_wg = round_up64(cdiv(m, target_wg), 64);
+  P.G = (int)cdiv(m, P.rows_per_wg);
+  P.gram_ld = round_up64(n + s, 16);
+  const int64_t gbn = round_up((int)(2 * s), 16);
+  P.partial_elems = P.gram_ld * gbn;
+  P.tsqr = make_tsqr_plan(m, (int)s);
+  size_t off = 0;
+  P.off_scratch_info = off; off = align256(off + sizeof(bcgs_info));
+  const size_t tri = (size_t)P.sp * P.sp * sizeof(double);
+  const size_t col = (size_t)(n + s) * P.sp * sizeof(double);
+  P.off_t1 = off; off = align256(off + tri);
+  P.off_t2 = off; off = align256(off + tri);
+  P.off_c1 = off; off = align256(off + col);
+  P.off_c2 = off; off = align256(off + col);
+  P.off_gram = off; off = align256(off + P.partial_elems * sizeof(double));
+  P.off_partial = off;
+  off = align256(off + (size_t)P.G * P.partial_elems * sizeof(double));
+  P.off_tsqr = off; off = align256(off + P.tsqr.total * sizeof(double));
+  P.bytes = off;
+  *p = P;
+  return true;
+}
+
+static int planned_syncs(int variant, int q) {
+  if (q == 1) return 1;
+  switch (variant) {
+    case BCGS_P_1S: return q + 1;
+    case BCGS_P_2S: return 2 * q;
+    default: return 4 * q - 3;
+  }
+}
+
+__global__ void info_init_kernel(bcgs_info* info, int syncs) {
+  if (threadIdx.x == 0) {
+    info->status = BCGS_OK;
+    info->block = -1;
+    info->pivot = -1;
+    info->stage = -1;
+    info->syncs = syncs;
+    info->reserved = 0;
+    info->value = 0.0;
+  }
+}
+
+// ------------------------------------------------------------ schedule ---
+template <typename T>
+struct Run {
+  Plan p;
+  const T* X; int64_t ldx;
+  T* Q; int64_t ldq;
+  double* R; int64_t ldr;
+  char* ws;
+  bcgs_info* info;
+  hipStream_t st;
+  hipError_t err = hipSuccess;
+
+  double* dws(size_t off) { return reinterpret_cast<double*>(ws + off); }
+  const T* xb(int j) const { return X + (int64_t)j * p.s * ldx; }
+  T* qb(int j) const { return Q + (int64_t)j * p.s * ldq; }
+  void check(hipError_t e) { if (err == hipSuccess && e != hipSuccess) err = e; }
+
+  // Description of one streaming pass.
+  struct Pass {
+    int nq = 0;                        // Q columns staged
+    const T* f = nullptr; int64_t ldf = 0;   // block F (s columns)
+    const T* e = nullptr; int64_t lde = 0;   // block E (s columns)
+    bool upd1 = false;                 // Q slot (nq/s - 1): U -> Q
+    bool upd2 = false; bool trsm2 = true;
+    const double* c2 = nullptr; const double* t2 = nullptr;
+    T* dst2 = nullptr;
+    bool gram = false; int gb0 = 0; int gbn = 0;
+    bool skip_eu = false;              // skip the E^T U tiles
+  };
+
+  void pass(const Pass& d) {
+    const int s = p.s;
+    PassArgs<T> a{};
+    a.m = p.m; a.s = s; a.sp = p.sp;
+    a.q = Q; a.ldq = ldq; a.nq = d.nq;
+    a.f = d.f; a.ldf = d.ldf; a.fcols = d.f ? s : 0;
+    a.e = d.e; a.lde = d.lde; a.ecols = d.e ? s : 0;
+    a.ncols = a.nq + a.fcols + a.ecols;
+    a.upd1 = d.upd1; a.u1_c0 = d.nq - s;
+    a.c1 = dws(p.off_c1); a.t1 = dws(p.off_t1);
+    a.dst1 = Q + (int64_t)(d.nq - s) * ldq; a.ldd1 = ldq;
+    a.upd2 = d.upd2; a.u2_c0 = d.nq; a.trsm2 = d.trsm2;
+    a.c2 = d.c2 ? d.c2 : dws(p.off_c2); a.t2 = d.t2 ? d.t2 : dws(p.off_t2);
+    a.dst2 = d.dst2; a.ldd2 = ldq;
+    a.gram = d.gram;
+    a.ga_p = round_up(a.ncols, 16);
+    a.gb0 = d.gb0; a.gbn_p = round_up(d.gbn > 0 ? d.gbn : 1, 16);
+    a.skip_a0 = d.skip_eu ? d.nq + s : 1 << 30;
+    a.skip_b1 = d.skip_eu ? s : 0;
+    a.partial = dws(p.off_partial);
+    int ncp = round_up(a.ncols, 16);
+    if (d.gram) ncp = std::max(ncp, std::max(a.ga_p, round_up(a.gb0 + a.gbn_p, 16)));
+    a.ncols_p = ncp;
+    // A blocks per wave limited by register budget (16 tiles per wave)
+    const int ntb = a.gbn_p / 16;
+    const int maxa = ntb >= 8 ? 2 : ntb >= 4 ? 4 : 8;
+    const int ta_total = a.ga_p / 16;
+    int groups = 1;
+    if (d.gram) groups = (int)cdiv(ta_total, kWaves * maxa);
+    if (groups > 1 && (d.upd1 || d.upd2)) {
+      // the Gram is split over several workgroups per row range: run the
+      // updates on their own first, then the Gram reading their results
+      Pass u = d;
+      u.gram = false;
+      pass(u);
+      Pass gdesc = d;
+      gdesc.upd1 = false;
+      gdesc.upd2 = false;
+      if (d.upd2) { gdesc.f = d.dst2; gdesc.ldf = ldq; }
+      pass(gdesc);
+      return;
+    }
+    a.groups = groups;
+    a.a_blocks_per_group = d.gram ? (int)cdiv(ta_total, groups) : 0;
+    // tile rows: largest that keeps two workgroups per CU
+    int tr = 64;
+    while (tr > 16) {
+      a.tr = tr;
+      if (pass_lds_bytes(a) <= 80 * 1024) break;
+      tr /= 2;
+    }
+    a.tr = tr;
+    a.rows_per_wg = p.rows_per_wg;
+    check(launch_pass(a, p.G, st));
+    if (d.gram)
+      check(launch_gram_reduce(a.partial, p.G, (int64_t)a.ga_p * a.gbn_p,
+                               dws(p.off_gram), st));
+    gram_ld_last = a.ga_p;
+  }
+  int64_t gram_ld_last = 0;
+
+  void epi(int mode, int j, bool has_e, bool chol_s) {
+    EpiArgs e{};
+    e.mode = mode; e.s = p.s; e.sp = p.sp; e.j = j;
+    e.has_e = has_e; e.chol_s = chol_s;
+    e.gram = dws(p.off_gram); e.gld = gram_ld_last;
+    e.c1 = dws(p.off_c1); e.c2 = dws(p.off_c2);
+    e.t1 = dws(p.off_t1); e.t2 = dws(p.off_t2);
+    e.r = R; e.ldr = ldr; e.info = info;
+    check(launch_epilogue(e, st));
+  }
+
+  void tsqr(const T* v, int64_t ldv, T* dst, double* rout, int64_t rs,
+            int64_t cs) {
+    check(launch_tsqr(p.tsqr, v, ldv, dst, ldq, p.m, dws(p.off_tsqr), rout,
+                      rs, cs, st));
+  }
+
+  void run() {
+    const int s = p.s, q = p.q, sp = p.sp;
+    check(launch_fill(R, p.n, p.n, ldr, 0.0, st));
+    hipLaunchKernelGGL(info_init_kernel, dim3(1), dim3(64), 0, st, info,
+                       planned_syncs(p.variant, q));
+    check(hipGetLastError());
+    // [Q_0, R_00] = TSQR(X_0)
+    tsqr(xb(0), ldx, qb(0), R, 1, ldr);
+    if (q == 1) return;
+    if (p.variant == BCGS_I_PLUS) { run_i_plus(); return; }
+    const bool one = p.variant == BCGS_P_1S;
+    {
+      Pass d;
+      d.nq = s; d.f = xb(1); d.ldf = ldx;
+      d.gram = true;
+      if (one) { d.gb0 = s; d.gbn = s; }      // [Q_0 X_1]^T X_1
+      else { d.gb0 = s; d.gbn = s; }          // Q_0^T X_1 (rows [0,s) used)
+      pass(d);
+      epi(one ? EPI_P1S_INIT : EPI_S_ONLY, 1, false, false);
+    }
+    for (int j = 1; j < q; ++j) {
+      const bool has_e = j < q - 1;
+      if (one) {
+        Pass d;
+        d.nq = j * s;
+        d.upd1 = j >= 2;
+        d.f = xb(j); d.ldf = ldx;
+        d.upd2 = true; d.trsm2 = true; d.dst2 = qb(j);
+        if (has_e) { d.e = xb(j + 1); d.lde = ldx; }
+        d.gram = true; d.gb0 = j * s; d.gbn = has_e ? 2 * s : s;
+        d.skip_eu = has_e;
+        pass(d);
+        epi(EPI_ONE_SYNC, j, has_e, true);
+      } else {
+        Pass u;                       // Q_{j-1} and V_j = X_j - Q S
+        u.nq = j * s; u.upd1 = j >= 2;
+        u.f = xb(j); u.ldf = ldx;
+        u.upd2 = true; u.trsm2 = false; u.dst2 = qb(j);
+        pass(u);
+        tsqr(qb(j), ldq, qb(j), dws(p.off_t2), sp, 1);   // U_j, S_jj
+        Pass d;                       // [Q_{0:j-1} U_j]^T [U_j X_{j+1}]
+        d.nq = (j + 1) * s;
+        if (has_e) { d.e = xb(j + 1); d.lde = ldx; }
+        d.gram = true; d.gb0 = j * s; d.gbn = has_e ? 2 * s : s;
+        d.skip_eu = has_e;
+        pass(d);
+        epi(EPI_ONE_SYNC, j, has_e, false);
+      }
+    }
+    Pass fin;                         // Q_{q-1} = (U - Q Y) Y_kk^{-1}
+    fin.nq = q * s; fin.upd1 = true;
+    pass(fin);
+  }
+
+  void run_i_plus() {
+    const int s = p.s, q = p.q, sp = p.sp;
+    for (int j = 1; j < q; ++j) {
+      Pass a1;                        // S = Q^T X_j
+      a1.nq = j * s; a1.f = xb(j); a1.ldf = ldx;
+      a1.gram = true; a1.gb0 = j * s; a1.gbn = s;
+      pass(a1);
+      epi(EPI_S_ONLY, j, false, false);
+      Pass a2;                        // V = X_j - Q S
+      a2.nq = j * s; a2.f = xb(j); a2.ldf = ldx;
+      a2.upd2 = true; a2.trsm2 = false; a2.dst2 = qb(j);
+      pass(a2);
+      tsqr(qb(j), ldq, qb(j), dws(p.off_t2), sp, 1);     // U_j, S_jj
+      Pass a3;                        // Y = Q^T U_j
+      a3.nq = j * s; a3.f = qb(j); a3.ldf = ldq;
+      a3.gram = true; a3.gb0 = j * s; a3.gbn = s;
+      pass(a3);
+      epi(EPI_Y_ONLY, j, false, false);
+      Pass a4;                        // W = U_j - Q Y
+      a4.nq = j * s; a4.f = qb(j); a4.ldf = ldq;
+      a4.upd2 = true; a4.trsm2 = false; a4.dst2 = qb(j);
+      a4.c2 = dws(p.off_c1);
+      pass(a4);
+      tsqr(qb(j), ldq, qb(j), dws(p.off_t1), sp, 1);     // Q_j, Y_jj
+      epi(EPI_R_ASSEMBLE, j, false, false);
+    }
+  }
+};
+
+template <typename T>
+static bcgs_status run_plan(const Plan& p, const T* X, int64_t ldx, T* Q,
+                            int64_t ldq, double* R, int64_t ldr, void* ws,
+                            bcgs_info* info, hipStream_t st) {
+  Run<T> r;
+  r.p = p; r.X = X; r.ldx = ldx; r.Q = Q; r.ldq = ldq; r.R = R; r.ldr = ldr;
+  r.ws = static_cast<char*>(ws); r.info = info; r.st = st;
+  r.run();
+  return r.err == hipSuccess ? BCGS_OK : BCGS_ERR_HIP;
+}
+
+// --------------------------------------------------- library workspace ---
+struct StreamWs {
+  void* ptr = nullptr;
+  size_t bytes = 0;
+  int device = -1;
+};
+static std::mutex g_mu;
+static std::map<hipStream_t, StreamWs> g_ws;
+
+static bool overlaps(const void* a, size_t an, const void* b, size_t bn) {
+  const char* pa = static_cast<const char*>(a);
+  const char* pb = static_cast<const char*>(b);
+  return pa < pb + bn && pb < pa + an;
+}
+
+}  // namespace bcgs
+
+using namespace bcgs;
+
+extern "C" {
+
+size_t bcgs_workspace_size(int64_t m, int64_t n, int64_t s,
+                           bcgs_variant variant, bcgs_precision precision) {
+  Plan p;
+  if (!make_plan(m, n, s, variant, precision, &p)) return 0;
+  return p.bytes;
+}
+
+int32_t bcgs_sync_count(int64_t m, int64_t n, int64_t s,
+                        bcgs_variant variant) {
+  if (!valid_args(m, n, s, variant, BCGS_FP64)) return -1;
+  return planned_syncs(variant, (int)(n / s));
+}
+
+bcgs_status bcgs_qr_ex(const void* X, int64_t ldx, int64_t m, int64_t n,
+                       int64_t s, bcgs_variant variant,
+                       bcgs_precision precision, void* Q, int64_t ldq,
+                       double* R, int64_t ldr, void* workspace,
+                       size_t ws_bytes, bcgs_info* d_info,
+                       hipStream_t stream) {
+  Plan p;
+  if (!X || !Q || !R || !workspace || !d_info) return BCGS_ERR_ARG;
+  if (!make_plan(m, n, s, variant, precision, &p)) return BCGS_ERR_ARG;
+  if (ldx < m || ldq < m || ldr < n) return BCGS_ERR_ARG;
+  if (ws_bytes < p.bytes) return BCGS_ERR_ARG;
+  if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0) return BCGS_ERR_ARG;
+  const size_t esz = precision == BCGS_FP64 ? 8 : 4;
+  const size_t xbytes = (size_t)((n - 1) * ldx + m) * esz;
+  const size_t qbytes = (size_t)((n - 1) * ldq + m) * esz;
+  if (overlaps(X, xbytes, Q, qbytes)) return BCGS_ERR_ARG;
+  if (overlaps(R, (size_t)((n - 1) * ldr + n) * 8, Q, qbytes) ||
+      overlaps(R, (size_t)((n - 1) * ldr + n) * 8, X, xbytes))
+    return BCGS_ERR_ARG;
+  if (precision == BCGS_FP32_BULK) return BCGS_ERR_UNSUPPORTED;
+  return run_plan<double>(p, static_cast<const double*>(X), ldx,
+                          static_cast<double*>(Q), ldq, R, ldr, workspace,
+                          d_info, stream);
+}
+
+bcgs_status bcgs_qr(const double* X, int64_t m, int64_t n, int64_t s,
+                    bcgs_variant variant, double* Q, double* R,
+                    hipStream_t stream) {
+  Plan p;
+  if (!X || !Q || !R) return BCGS_ERR_ARG;
+  if (!make_plan(m, n, s, variant, BCGS_FP64, &p)) return BCGS_ERR_ARG;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return BCGS_ERR_HIP;
+  void* ws = nullptr;
+  {
+    std::lock_guard<std::mutex> lock(g_mu);
+    StreamWs& w = g_ws[stream];
+    if (w.bytes < p.bytes || w.device != dev) {
+      if (w.ptr) {
+        if (hipStreamSynchronize(stream) != hipSuccess) return BCGS_ERR_HIP;
+        (void)hipFree(w.ptr);
+        w.ptr = nullptr;
+        w.bytes = 0;
+      }
+      if (hipMalloc(&w.ptr, p.bytes) != hipSuccess) {
+        w.ptr = nullptr;
+        return BCGS_ERR_NOMEM;
+      }
+      w.bytes = p.bytes;
+      w.device = dev;
+    }
+    ws = w.ptr;
+  }
+  bcgs_info* info = reinterpret_cast<bcgs_info*>(
+      static_cast<char*>(ws) + p.off_scratch_info);
+  return bcgs_qr_ex(X, m, m, n, s, variant, BCGS_FP64, Q, m, R, n, ws,
+                    p.bytes, info, stream);
+}
+
+bcgs_status bcgs_get_info(hipStream_t stream, bcgs_info* host_out) {
+  if (!host_out) return BCGS_ERR_ARG;
+  void* ptr;
+  {
+    std::lock_guard<std::mutex> lock(g_mu);
+    auto it = g_ws.find(stream);
+    if (it == g_ws.end() || !it->second.ptr) return BCGS_ERR_ARG;
+    ptr = it->second.ptr;
+  }
+  if (hipStreamSynchronize(stream) != hipSuccess) return BCGS_ERR_HIP;
+  if (hipMemcpy(host_out, ptr, sizeof(bcgs_info), hipMemcpyDeviceToHost) !=
+      hipSuccess)
+    return BCGS_ERR_HIP;
+  return BCGS_OK;
+}
+
+void bcgs_release(void) {
+  std::lock_guard<std::mutex> lock(g_mu);
+  for (auto& kv : g_ws) {
+    if (kv.second.ptr) {
+      (void)hipStreamSynchronize(kv.first);
+      (void)hipFree(kv.second.ptr);
+    }
+  }
+  g_ws.clear();
+}
+
+const char* bcgs_status_string(bcgs_status st) {
+  switch (st) {
+    case BCGS_OK: return "ok";
+    case BCGS_ERR_ARG: return "invalid argument";
+    case BCGS_ERR_BREAKDOWN: return "Cholesky breakdown";
+    case BCGS_ERR_NOMEM: return "out of device memory";
+    case BCGS_ERR_HIP: return "HIP runtime error";
+    case BCGS_ERR_QUEUE_FULL: return "queue full";
+    case BCGS_PENDING: return "pending";
+    case BCGS_ERR_UNSUPPORTED: return "unsupported";
+  }
+  return "unknown status";
+}
+
+}  // extern "C"

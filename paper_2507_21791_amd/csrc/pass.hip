@@ -1,0 +1,279 @@
+// Streaming pass over the m rows: block updates and tall-skinny Gram
+// products of Alg. 1 / Alg. 2 (and of BCGSI+), fused per row tile.
+//
+// One workgroup owns a contiguous row range and walks it in tiles of TR
+// rows.  Per tile:
+//   1. stage the needed column window in LDS (coalesced: consecutive lanes
+//      read consecutive rows of one column; rows past m are zero),
+//   2. optional block update 1 (Q_k = (U_k - Q_{1:k-1} Y) Y_kk^{-1}),
+//   3. optional block update 2 (U_{k+1} = (X_{k+1} - Q_{1:k} S) S^{-1}, or
+//      V = X_{k+1} - Q_{1:k} S without the triangular factor),
+//      both as FP64 MFMA products followed by a row-wise substitution with
+//      the upper-triangular factor, written back to HBM in place,
+//   4. optional Gram accumulation A^T B of LDS columns (the tall-skinny
+//      products that the paper's synchronizations reduce, section 3) with
+//      FP64 MFMA; each wave keeps a fixed set of 16x16 output tiles in
+//      registers for the whole row range.
+// The partial Gram matrices of all workgroups are then summed in a fixed
+// order by gram_reduce_kernel, so results do not depend on timing.
+//
+// MFMA v_mfma_f64_16x16x4f64 operand layout (lane l of 64):
+//   A (16 x 4): A[l % 16][l / 16]     B (4 x 16): B[l / 16][l % 16]
+//   D (16 x 16), 4 values v:          D[l / 16 + 4 * v][l % 16]
+#include "common.h"
+
+namespace bcgs {
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ v4d mfma_f64(double a, double b, v4d c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+template <typename T>
+__device__ __forceinline__ const T* col_src(const PassArgs<T>& a, int c,
+                                            int64_t* ld) {
+  if (c < a.nq) { *ld = a.ldq; return a.q + (int64_t)c * a.ldq; }
+  c -= a.nq;
+  if (c < a.fcols) { *ld = a.ldf; return a.f + (int64_t)c * a.ldf; }
+  c -= a.fcols;
+  *ld = a.lde;
+  return a.e + (int64_t)c * a.lde;
+}
+
+// Block update of the tile columns [uc0, uc0 + s):
+//   W = tile[:, uc0:uc0+s] - tile[:, 0:uc0] * C        (MFMA, K = uc0)
+//   Y = W * T^{-1}  (if trsm; row-wise substitution)    -> tile and HBM.
+template <typename T>
+__device__ void block_update(const PassArgs<T>& a, double* tile, int trp,
+                             double* scr, int uc0, const double* __restrict__ C,
+                             const double* __restrict__ Tm,
+                             const double* rdiag, bool trsm, T* dst,
+                             int64_t ldd, int64_t r0, int rows) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tr = a.tr, sp = a.sp, s = a.s;
+  const int mb = tr >> 4, nb = sp >> 4, nt = mb * nb;
+  const int ksplit = nt >= kWaves ? 1 : kWaves / nt;
+  const int K = uc0;
+  const int ksteps = (K + 3) >> 2;
+  const int kper = (ksteps + ksplit - 1) / ksplit;
+  const int srow = sp + 1;     // padded scratch row
+  const int li = lane & 15, lk = lane >> 4;
+  for (int task = wave; task < nt * ksplit; task += kWaves) {
+    const int t = task % nt, ks = task / nt;
+    const int rb = t % mb, cb = t / mb;
+    v4d acc = {0.0, 0.0, 0.0, 0.0};
+    const int kb = ks * kper, ke = min(ksteps, kb + kper);
+    for (int kk = kb; kk < ke; ++kk) {
+      const int k = kk * 4 + lk;
+      double av = 0.0, bv = 0.0;
+      if (k < K) {
+        av = tile[k * trp + rb * 16 + li];
+        bv = C[k * sp + cb * 16 + li];
+      }
+      acc = mfma_f64(av, bv, acc);
+    }
+    double* out = scr + (size_t)ks * tr * srow;
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+      out[(rb * 16 + lk + 4 * v) * srow + cb * 16 + li] = acc[v];
+  }
+  __syncthreads();
+  if (tid < tr) {
+    const int r = tid;
+    double* w = scr + r * srow;  // this row's workspace (slice ks = 0)
+    for (int c = 0; c < s; ++c) {
+      double sum = 0.0;
+      for (int ks = 0; ks < ksplit; ++ks)
+        sum += scr[(size_t)ks * tr * srow + r * srow + c];
+      w[c] = tile[(uc0 + c) * trp + r] - sum;
+    }
+    if (trsm) {
+      // W T^{-1}: y_j = (w_j - sum_{i<j} y_i T_ij) / T_jj, column-oriented
+      for (int j = 0; j < s; ++j) {
+        const double yj = w[j] * rdiag[j];
+        w[j] = yj;
+        for (int l = j + 1; l < s; ++l) w[l] -= yj * Tm[j * sp + l];
+      }
+    }
+    for (int c = 0; c < s; ++c) tile[(uc0 + c) * trp + r] = w[c];
+    if (r < rows)
+      for (int c = 0; c < s; ++c)
+        dst[(int64_t)c * ldd + r0 + r] = static_cast<T>(w[c]);
+  }
+  __syncthreads();
+}
+
+template <typename T, bool GRAM, int NTB, int MAXA>
+__global__ __launch_bounds__(kThreads) void pass_kernel(PassArgs<T> a) {
+  extern __shared__ double lds[];
+  const int tr = a.tr, trp = tr + 1;
+  double* tile = lds;
+  double* rdiag = tile + (size_t)a.ncols_p * trp;   // 2 * 64
+  double* scr = rdiag + 2 * kMaxS;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int h = blockIdx.x % a.groups;
+  const int64_t g = blockIdx.x / a.groups;
+  const int64_t row_begin = g * a.rows_per_wg;
+  const int64_t row_end = min(a.m, row_begin + a.rows_per_wg);
+
+  if (tid < a.s) {
+    if (a.upd1) rdiag[tid] = 1.0 / a.t1[tid * a.sp + tid];
+    if (a.upd2 && a.trsm2) rdiag[kMaxS + tid] = 1.0 / a.t2[tid * a.sp + tid];
+  }
+
+  v4d acc[MAXA][NTB];
+  int ta_of[MAXA];
+  const int ta_total = a.ga_p >> 4;
+  const int ta_lo = h * a.a_blocks_per_group;
+  const int ta_hi = min(ta_total, ta_lo + a.a_blocks_per_group);
+#pragma unroll
+  for (int i = 0; i < MAXA; ++i) {
+    ta_of[i] = ta_lo + wave + kWaves * i;
+#pragma unroll
+    for (int b = 0; b < NTB; ++b) acc[i][b] = v4d{0.0, 0.0, 0.0, 0.0};
+  }
+  __syncthreads();
+
+  const int tr_shift = __ffs(tr) - 1;
+  const int nstage = a.ncols_p << tr_shift;
+  for (int64_t r0 = row_begin; r0 < row_end; r0 += tr) {
+    const int rows = (int)min((int64_t)tr, row_end - r0);
+    // 1. stage the column window (zero past m and past ncols)
+    for (int idx = tid; idx < nstage; idx += kThreads) {
+      const int c = idx >> tr_shift, r = idx & (tr - 1);
+      double v = 0.0;
+      if (r < rows && c < a.ncols) {
+        int64_t ld;
+        const T* src = col_src(a, c, &ld);
+        v = static_cast<double>(src[r0 + r]);
+      }
+      tile[c * trp + r] = v;
+    }
+    __syncthreads();
+    // 2-3. block updates
+    if (a.upd1)
+      block_update(a, tile, trp, scr, a.u1_c0, a.c1, a.t1, rdiag, true,
+                   a.dst1, a.ldd1, r0, rows);
+    if (a.upd2)
+      block_update(a, tile, trp, scr, a.u2_c0, a.c2, a.t2, rdiag + kMaxS,
+                   a.trsm2 != 0, a.dst2, a.ldd2, r0, rows);
+    // 4. Gram accumulation over this tile's rows
+    if (GRAM) {
+      for (int kk = 0; kk < tr; kk += 4) {
+        const int r = kk + lk;
+        double bf[NTB];
+#pragma unroll
+        for (int b = 0; b < NTB; ++b)
+          bf[b] = tile[(a.gb0 + b * 16 + li) * trp + r];
+#pragma unroll
+        for (int i = 0; i < MAXA; ++i) {
+          const int ta = ta_of[i];
+          if (ta < ta_hi) {
+            const double af = tile[(ta * 16 + li) * trp + r];
+#pragma unroll
+            for (int b = 0; b < NTB; ++b) {
+              if (ta * 16 >= a.skip_a0 && b * 16 + 16 <= a.skip_b1) continue;
+              acc[i][b] = mfma_f64(af, bf[b], acc[i][b]);
+            }
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+
+  if (GRAM) {
+    double* out = a.partial + (size_t)g * a.ga_p * a.gbn_p;
+#pragma unroll
+    for (int i = 0; i < MAXA; ++i) {
+      const int ta = ta_of[i];
+      if (ta >= ta_hi) continue;
+#pragma unroll
+      for (int b = 0; b < NTB; ++b) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+          out[(size_t)(b * 16 + li) * a.ga_p + ta * 16 + lk + 4 * v] =
+              acc[i][b][v];
+      }
+    }
+  }
+}
+
+// Fixed-order sum of the per-workgroup partial Gram matrices:
+// out[e] = sum_g partial[g][e], four interleaved partial sums per entry
+// combined in a fixed order.
+__global__ __launch_bounds__(kThreads) void gram_reduce_kernel(
+    const double* __restrict__ partial, int G, int64_t elems,
+    double* __restrict__ out) {
+  __shared__ double red[kWaves][64];
+  const int tid = threadIdx.x, lane = tid & 63, sub = tid >> 6;
+  const int64_t e = (int64_t)blockIdx.x * 64 + lane;
+  double acc = 0.0;
+  if (e < elems)
+    for (int g = sub; g < G; g += kWaves) acc += partial[(size_t)g * elems + e];
+  red[sub][lane] = acc;
+  __syncthreads();
+  if (sub == 0 && e < elems) {
+    double t = red[0][lane];
+#pragma unroll
+    for (int w = 1; w < kWaves; ++w) t += red[w][lane];
+    out[e] = t;
+  }
+}
+
+hipError_t launch_gram_reduce(const double* partial, int G, int64_t elems,
+                              double* out, hipStream_t st) {
+  const int64_t blocks = cdiv(elems, 64);
+  hipLaunchKernelGGL(gram_reduce_kernel, dim3((unsigned)blocks),
+                     dim3(kThreads), 0, st, partial, G, elems, out);
+  return hipGetLastError();
+}
+
+template <typename T>
+size_t pass_lds_bytes(const PassArgs<T>& a) {
+  const int nt = (a.tr / 16) * (a.sp / 16);
+  const int ksplit = nt >= kWaves ? 1 : kWaves / nt;
+  size_t d = (size_t)a.ncols_p * (a.tr + 1) + 2 * kMaxS +
+             (size_t)ksplit * a.tr * (a.sp + 1);
+  return d * sizeof(double);
+}
+
+template <typename T, bool GRAM, int NTB, int MAXA>
+static hipError_t launch_one(const PassArgs<T>& a, int G, hipStream_t st) {
+  auto kern = pass_kernel<T, GRAM, NTB, MAXA>;
+  const size_t lds = pass_lds_bytes(a);
+  static bool attr_done = false;
+  if (!attr_done) {
+    (void)hipFuncSetAttribute((const void*)kern,
+                        hipFuncAttributeMaxDynamicSharedMemorySize,
+                        160 * 1024);
+    attr_done = true;
+  }
+  hipLaunchKernelGGL(kern, dim3((unsigned)(G * a.groups)), dim3(kThreads),
+                     lds, st, a);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_pass(const PassArgs<T>& a, int G, hipStream_t st) {
+  if (!a.gram) return launch_one<T, false, 1, 1>(a, G, st);
+  const int ntb = a.gbn_p / 16;
+  const int maxa = (a.a_blocks_per_group + kWaves - 1) / kWaves;
+#define BCGS_TRY(NTB_, MAXA_)                                  \
+  if (ntb == NTB_ && maxa <= MAXA_)                            \
+    return launch_one<T, true, NTB_, MAXA_>(a, G, st);
+  BCGS_TRY(1, 1) BCGS_TRY(1, 2) BCGS_TRY(1, 4) BCGS_TRY(1, 8)
+  BCGS_TRY(2, 1) BCGS_TRY(2, 2) BCGS_TRY(2, 4) BCGS_TRY(2, 8)
+  BCGS_TRY(4, 1) BCGS_TRY(4, 2) BCGS_TRY(4, 4)
+  BCGS_TRY(8, 1) BCGS_TRY(8, 2)
+#undef BCGS_TRY
+  return hipErrorInvalidValue;
+}
+
+template hipError_t launch_pass<double>(const PassArgs<double>&, int,
+                                        hipStream_t);
+template size_t pass_lds_bytes<double>(const PassArgs<double>&);
+
+}  // namespace bcgs

@@ -1,0 +1,112 @@
+"""The C ABI on the CPU: the library loads, exports every function bcgs.h
+declares, sizes workspaces, reports sync counts, and rejects bad arguments
+synchronously (before any device work)."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2507_21791_amd import bcgs
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    names = set()
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if not fn.endswith(".h"):
+            continue
+        src = open(os.path.join(ROOT, "include", fn)).read()
+        src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+        for m in re.finditer(r"^[A-Za-z_][\w\s\*]*?\b(bcgs_\w+)\s*\(", src,
+                             flags=re.M):
+            names.add(m.group(1))
+    return names
+
+
+def test_library_exports_every_declared_symbol():
+    L = bcgs.lib()
+    names = _declared_functions()
+    assert {"bcgs_qr", "bcgs_qr_ex", "bcgs_workspace_size",
+            "bcgs_sync_count", "bcgs_get_info"} <= names
+    missing = [n for n in names if not hasattr(L, n)]
+    assert not missing, missing
+
+
+def test_info_struct_layout():
+    assert ctypes.sizeof(bcgs.Info) == 32
+    assert bcgs.Info.value.offset == 24
+
+
+@pytest.mark.parametrize("variant,q,want", [
+    ("p-1s", 16, 17), ("p-2s", 16, 32), ("bcgsi+", 16, 61),
+    ("p-1s", 1, 1), ("p-2s", 1, 1), ("bcgsi+", 1, 1), ("p-1s", 2, 3)])
+def test_sync_counts(variant, q, want):
+    assert bcgs.sync_count(1000, 4 * q, 4, variant) == want
+
+
+def test_workspace_size_is_modest():
+    ws = bcgs.workspace_size(1 << 22, 256, 16, "p-1s")
+    assert 0 < ws < 256 << 20          # partial Grams + TSQR tree, not m*n
+    assert bcgs.workspace_size(100, 7, 2, "p-1s") == 0     # s does not divide n
+    assert bcgs.workspace_size(5, 8, 4, "p-1s") == 0       # m < n
+    assert bcgs.workspace_size(100, 128, 128, "p-1s") == 0  # s > 64
+
+
+FAKE = ctypes.c_void_p(0x10000)   # never dereferenced: the checks fail first
+
+
+@pytest.mark.parametrize("m,n,s,ldx,ldq,ldr,variant,prec", [
+    (100, 8, 3, 100, 100, 8, 2, 0),     # s does not divide n
+    (7, 8, 4, 7, 7, 8, 2, 0),           # m < n
+    (100, 8, 0, 100, 100, 8, 2, 0),     # s < 1
+    (100, 8, 4, 99, 100, 8, 2, 0),      # ldx < m
+    (100, 8, 4, 100, 50, 8, 2, 0),      # ldq < m
+    (100, 8, 4, 100, 100, 7, 2, 0),     # ldr < n
+    (100, 8, 4, 100, 100, 8, 9, 0),     # unknown variant
+    (100, 8, 4, 100, 100, 8, 2, 5),     # unknown precision
+])
+def test_bad_arguments_rejected_synchronously(m, n, s, ldx, ldq, ldr,
+                                              variant, prec):
+    L = bcgs.lib()
+    st = L.bcgs_qr_ex(FAKE, ldx, m, n, s, variant, prec,
+                      ctypes.c_void_p(0x9000000), ldq,
+                      ctypes.c_void_p(0x20000000), ldr,
+                      ctypes.c_void_p(0x40000000), 1 << 40,
+                      ctypes.c_void_p(0x80000000), None)
+    assert st == bcgs.BCGS_ERR_ARG
+
+
+def test_null_and_aliasing_rejected():
+    L = bcgs.lib()
+    args = dict(m=100, n=8, s=4)
+    # null workspace
+    assert L.bcgs_qr_ex(FAKE, 100, 100, 8, 4, 2, 0, ctypes.c_void_p(0x900000),
+                        100, ctypes.c_void_p(0x2000000), 8, None, 1 << 30,
+                        ctypes.c_void_p(0x8000000), None) == bcgs.BCGS_ERR_ARG
+    # Q overlapping X
+    assert L.bcgs_qr_ex(ctypes.c_void_p(0x100000), 100, 100, 8, 4, 2, 0,
+                        ctypes.c_void_p(0x100000 + 800), 100,
+                        ctypes.c_void_p(0x2000000), 8,
+                        ctypes.c_void_p(0x4000000), 1 << 30,
+                        ctypes.c_void_p(0x8000000), None) == bcgs.BCGS_ERR_ARG
+    # workspace too small
+    assert L.bcgs_qr_ex(FAKE, 100, 100, 8, 4, 2, 0, ctypes.c_void_p(0x900000),
+                        100, ctypes.c_void_p(0x2000000), 8,
+                        ctypes.c_void_p(0x4000000), 16,
+                        ctypes.c_void_p(0x8000000), None) == bcgs.BCGS_ERR_ARG
+    # misaligned workspace
+    assert L.bcgs_qr_ex(FAKE, 100, 100, 8, 4, 2, 0, ctypes.c_void_p(0x900000),
+                        100, ctypes.c_void_p(0x2000000), 8,
+                        ctypes.c_void_p(0x4000008), 1 << 30,
+                        ctypes.c_void_p(0x8000000), None) == bcgs.BCGS_ERR_ARG
+    assert L.bcgs_qr(None, 100, 8, 4, 2, FAKE, FAKE, None) == bcgs.BCGS_ERR_ARG
+    del args
+
+
+def test_status_strings():
+    L = bcgs.lib()
+    assert L.bcgs_status_string(0) == b"ok"
+    assert L.bcgs_status_string(2) == b"Cholesky breakdown"

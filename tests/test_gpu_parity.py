@@ -1,0 +1,136 @@
+"""GPU (gfx950) results against the FP64 oracle, through the C ABI.
+
+Every case prints its name before touching the GPU.  Tolerances: see
+tests/parity.py.
+"""
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2507_21791_amd import workloads as W
+
+from parity import compare, host, log, run_gpu
+
+pytestmark = pytest.mark.gpu
+VARIANTS = ["bcgsi+", "p-2s", "p-1s"]
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _lib():
+    import torch
+    from paper_2507_21791_amd import bcgs
+    assert torch.cuda.is_available()
+    bcgs.lib()
+    yield
+    bcgs.lib().bcgs_release()
+
+
+@pytest.mark.parametrize("variant", VARIANTS)
+def test_small_workload(variant):
+    """2000 x 80, s = 8, kappa = 1e6 (10 block columns)."""
+    w = W.WORKLOADS["small"]
+    log(f"[gpu] small workload {variant}")
+    X = W.make_host("small")
+    Qg, Rg, info = run_gpu(X, w["s"], variant)
+    out = compare(X, w["s"], variant, host(Qg), host(Rg), info, kappa=1e6)
+    log("   ", out)
+
+
+SHAPES = [  # (m, n, s, decades)
+    (64, 8, 4, 2), (65, 12, 4, 2), (100, 8, 8, 1), (300, 48, 16, 3),
+    (1000, 64, 16, 4), (257, 48, 1, 2), (257, 48, 2, 3), (257, 48, 3, 3),
+    (513, 60, 5, 3), (40, 40, 8, 1), (2000, 128, 32, 3), (3000, 128, 64, 3),
+    (4099, 96, 16, 5), (10000, 24, 8, 2), (777, 16, 16, 3), (777, 32, 16, 3),
+    (33000, 48, 16, 4),
+]
+
+
+@pytest.mark.parametrize("variant", VARIANTS)
+@pytest.mark.parametrize("m,n,s,dec", SHAPES)
+def test_shapes(m, n, s, dec, variant):
+    log(f"[gpu] shape m={m} n={n} s={s} kappa=1e{dec} {variant}")
+    X = W.conditioned_host(m, n, dec, seed=m + n + s)
+    Qg, Rg, info = run_gpu(X, s, variant)
+    compare(X, s, variant, host(Qg), host(Rg), info, kappa=10.0 ** dec)
+
+
+@pytest.mark.parametrize("decades", [6, 8])
+@pytest.mark.parametrize("variant", VARIANTS)
+def test_tall_reduced_rows(variant, decades):
+    """The 4M x 256, s = 16 workload's column structure at 2^16 + 37 rows."""
+    m = (1 << 16) + 37
+    log(f"[gpu] tall reduced m={m} n=256 s=16 kappa=1e{decades} {variant}")
+    X = W.conditioned_host(m, 256, decades, seed=2)
+    Qg, Rg, info = run_gpu(X, 16, variant)
+    out = compare(X, 16, variant, host(Qg), host(Rg), info,
+                  kappa=10.0 ** decades)
+    log("   ", out, info.as_dict())
+
+
+@pytest.mark.parametrize("s", [4, 8, 16, 32, 64])
+@pytest.mark.parametrize("variant", VARIANTS)
+def test_sweep_reduced_rows(variant, s):
+    """The 1M x 512 block-size sweep workload at 2^15 + 5 rows."""
+    m = (1 << 15) + 5
+    log(f"[gpu] sweep reduced m={m} n=512 s={s} {variant}")
+    X = W.gaussian_plus_structured_host(m, 512, 10, 1e-2, seed=3)
+    Qg, Rg, info = run_gpu(X, s, variant)
+    compare(X, s, variant, host(Qg), host(Rg), info)
+
+
+@pytest.mark.parametrize("variant", VARIANTS)
+def test_exact_case_bitwise(variant):
+    """Scaled permuted identity: every step is exact, so the GPU must return
+    R = diag(2^e) and Q = X diag(2^-e) bit for bit (same closed form the
+    oracle reproduces exactly)."""
+    log(f"[gpu] exact scaled permuted identity {variant}")
+    n = 64
+    e = np.random.default_rng(3).integers(-20, 20, size=n)
+    X = W.scaled_permuted_identity(3000, n, e, seed=3)
+    Qg, Rg, info = run_gpu(X, 16, variant)
+    assert info.status == 0
+    assert np.array_equal(host(Rg), np.diag(np.ldexp(1.0, e)))
+    assert np.array_equal(host(Qg), X * np.ldexp(1.0, -e)[None, :])
+
+
+@pytest.mark.parametrize("variant", ["p-1s"])
+def test_breakdown_same_block(variant):
+    """Duplicate columns: exact rank deficiency; the Cholesky variant breaks
+    down in the block where the oracle does, without crashing."""
+    log(f"[gpu] breakdown duplicate columns {variant}")
+    X = W.conditioned_host(500, 32, 2, seed=6)
+    X[:, 20] = X[:, 3]
+    Qg, Rg, info = run_gpu(X, 8, variant)
+    r = O.qr(X, 8, variant)
+    assert r.breakdown is not None and info.status == 2
+    assert info.block == r.breakdown.block
+    assert np.isnan(host(Rg)).any()
+
+
+@pytest.mark.parametrize("variant", VARIANTS)
+def test_bitwise_repeatable_and_sync_count(variant):
+    from paper_2507_21791_amd import bcgs
+    log(f"[gpu] repeatability {variant}")
+    X = W.conditioned_host(20000, 64, 5, seed=9)
+    a = run_gpu(X, 16, variant)
+    b = run_gpu(X, 16, variant)
+    assert np.array_equal(host(a[0]), host(b[0]))
+    assert np.array_equal(host(a[1]), host(b[1]))
+    want = bcgs.sync_count(20000, 64, 16, variant)
+    assert a[2].syncs == want == O.qr(X, 16, variant).syncs
+
+
+def test_library_owned_workspace_entry_point():
+    import torch
+    from paper_2507_21791_amd import bcgs
+    log("[gpu] bcgs_qr with library workspace")
+    X = W.conditioned_host(3000, 64, 4, seed=10)
+    Xd = torch.from_numpy(X).cuda()
+    Xd = Xd.t().contiguous().t()
+    Q = bcgs.empty_fortran(3000, 64, torch.float64, "cuda")
+    R = bcgs.empty_fortran(64, 64, torch.float64, "cuda")
+    bcgs.qr_simple(Xd, 8, "p-1s", Q, R)
+    info = bcgs.get_info()
+    assert info.status == 0 and info.syncs == 9
+    compare(X, 8, "p-1s", host(Q), host(R), info, kappa=1e4)
