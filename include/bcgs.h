@@ -136,6 +136,43 @@ bcgs_status bcgs_get_info(hipStream_t stream, bcgs_info* host_out);
 /* Frees the library-owned workspaces of every stream (waits for them). */
 void bcgs_release(void);
 
+/* ---- launch profiling ----------------------------------------------------
+ * Between bcgs_profile_start(stream) and bcgs_profile_stop(stream, ...), every
+ * kernel the library enqueues on `stream` is bracketed by HIP events and
+ * tagged with its ALGORITHMIC HBM bytes and flops: the data the method must
+ * read and write and the arithmetic it must do for that step (per-row cost
+ * times rows), not what the kernel actually moves.  Timing the events adds
+ * a few microseconds per launch. */
+enum {
+    BCGS_KERNEL_PASS = 0,        /* streaming pass: block updates + Gram */
+    BCGS_KERNEL_REDUCE = 1,      /* fixed-order sum of partial Grams */
+    BCGS_KERNEL_EPILOGUE = 2,    /* s x s Cholesky, eq. (1), R assembly */
+    BCGS_KERNEL_TSQR_LEAF = 3,   /* TSQR: per-chunk Householder R factors */
+    BCGS_KERNEL_TSQR_NODE = 4,   /* TSQR: one level of the reduction tree */
+    BCGS_KERNEL_TSQR_DOWN = 5,   /* TSQR: downward coefficients */
+    BCGS_KERNEL_TSQR_APPLY = 6,  /* TSQR: explicit Q rows */
+    BCGS_KERNEL_OTHER = 7
+};
+
+/* One profiled launch.  tag identifies the kernel instantiation (for
+ * BCGS_KERNEL_PASS: 100*gram + 10*B tiles + A tiles per wave). */
+typedef struct {
+    int32_t kind;
+    int32_t tag;
+    double ms;
+    double bytes;
+    double flops;
+} bcgs_launch_record;
+
+/* Start recording launches on `stream` (host-side; no device call). */
+bcgs_status bcgs_profile_start(hipStream_t stream);
+
+/* Wait for `stream`, write up to `capacity` records (host array, may be
+ * NULL) in launch order, stop recording, and return the number of launches
+ * recorded (-1 if profiling was not started on the stream). */
+int32_t bcgs_profile_stop(hipStream_t stream, bcgs_launch_record* out,
+                          int32_t capacity);
+
 /* Human-readable name of a status code (static string). */
 const char* bcgs_status_string(bcgs_status status);
 

@@ -34,6 +34,16 @@ class Info(ctypes.Structure):
 
 
 INFO_BYTES = ctypes.sizeof(Info)
+
+KERNEL_KINDS = {0: "pass", 1: "reduce", 2: "epilogue", 3: "tsqr_leaf",
+                4: "tsqr_node", 5: "tsqr_down", 6: "tsqr_apply", 7: "other"}
+
+
+class LaunchRecord(ctypes.Structure):
+    """Mirror of bcgs_launch_record."""
+    _fields_ = [("kind", ctypes.c_int32), ("tag", ctypes.c_int32),
+                ("ms", ctypes.c_double), ("bytes", ctypes.c_double),
+                ("flops", ctypes.c_double)]
 _lib = None
 
 _PROTOS = {
@@ -56,6 +66,9 @@ _PROTOS = {
     "bcgs_get_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Info)]),
     "bcgs_release": (None, []),
     "bcgs_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+    "bcgs_profile_start": (ctypes.c_int, [ctypes.c_void_p]),
+    "bcgs_profile_stop": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p,
+                                           ctypes.c_int32]),
 }
 
 
@@ -170,6 +183,22 @@ def qr_simple(X, s, variant, Q, R, stream=None):
     if st != BCGS_OK:
         raise BcgsError(st, "bcgs_qr")
     return Q, R
+
+
+def profile_start(stream=None):
+    lib().bcgs_profile_start(_stream_handle(stream))
+
+
+def profile_stop(stream=None, capacity=1 << 16):
+    """Stop profiling the stream; returns a list of launch dicts
+    (kind, tag, ms, bytes, flops) in launch order."""
+    recs = (LaunchRecord * capacity)()
+    n = lib().bcgs_profile_stop(_stream_handle(stream), recs, capacity)
+    if n < 0:
+        raise BcgsError(BCGS_ERR_ARG, "bcgs_profile_stop")
+    return [{"kind": KERNEL_KINDS.get(r.kind, r.kind), "tag": r.tag,
+             "ms": r.ms, "bytes": r.bytes, "flops": r.flops}
+            for r in recs[:min(n, capacity)]]
 
 
 def get_info(stream=None):

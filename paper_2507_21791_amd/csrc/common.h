@@ -104,8 +104,9 @@ bool make_plan(int64_t m, int64_t n, int64_t s, int variant, int precision,
                Plan* p);
 
 // Launchers (return hipError_t of the launch).
+// *tag receives the kernel instantiation (see bcgs_launch_record).
 template <typename T>
-hipError_t launch_pass(const PassArgs<T>& a, int G, hipStream_t st);
+hipError_t launch_pass(const PassArgs<T>& a, int G, hipStream_t st, int* tag);
 hipError_t launch_gram_reduce(const double* partial, int G, int64_t elems,
                               double* out, hipStream_t st);
 
@@ -143,5 +144,12 @@ struct EpiArgs {
   double* r; int64_t ldr;
   bcgs_info* info;
 };
+
+// launch profiling (profile.hip); no-ops unless bcgs_profile_start ran on
+// the stream being attached
+void prof_attach(hipStream_t st);
+void prof_detach();
+void prof_begin(int kind, int tag, double bytes, double flops);
+void prof_end();
 
 }  // namespace bcgs

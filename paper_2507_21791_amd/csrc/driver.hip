@@ -85,6 +85,8 @@ static int planned_syncs(int variant, int q) {
   }
 }
 
+void prof_retag(int tag);
+
 __global__ void info_init_kernel(bcgs_info* info, int syncs) {
   if (threadIdx.x == 0) {
     info->status = BCGS_OK;
@@ -125,6 +127,7 @@ struct Run {
     T* dst2 = nullptr;
     bool gram = false; int gb0 = 0; int gbn = 0;
     bool skip_eu = false;              // skip the E^T U tiles
+    int64_t needed = 0;                // Gram entries the method needs
   };
 
   void pass(const Pass& d) {
@@ -180,7 +183,22 @@ struct Run {
     }
     a.tr = tr;
     a.rows_per_wg = p.rows_per_wg;
-    check(launch_pass(a, p.G, st));
+    // algorithmic work of this pass: the staged columns are read once, the
+    // updated blocks written once; 2 K s flops per row and block update
+    // plus s^2 for the triangular solve; 2 flops per needed Gram entry
+    const double mr = (double)p.m, esz = sizeof(T);
+    double flops = 0.0, cols_rw = a.ncols;
+    if (d.upd1) { flops += mr * (2.0 * a.u1_c0 * s + (double)s * s); cols_rw += s; }
+    if (d.upd2) {
+      flops += mr * (2.0 * a.u2_c0 * s + (d.trsm2 ? (double)s * s : 0.0));
+      cols_rw += s;
+    }
+    if (d.gram) flops += 2.0 * mr * (double)d.needed;
+    int tag = 0;
+    prof_begin(BCGS_KERNEL_PASS, -1, esz * mr * cols_rw, flops);
+    check(launch_pass(a, p.G, st, &tag));
+    prof_end();
+    prof_retag(tag);
     if (d.gram)
       check(launch_gram_reduce(a.partial, p.G, (int64_t)a.ga_p * a.gbn_p,
                                dws(p.off_gram), st));
@@ -206,6 +224,12 @@ struct Run {
   }
 
   void run() {
+    prof_attach(st);
+    run_steps();
+    prof_detach();
+  }
+
+  void run_steps() {
     const int s = p.s, q = p.q, sp = p.sp;
     check(launch_fill(R, p.n, p.n, ldr, 0.0, st));
     hipLaunchKernelGGL(info_init_kernel, dim3(1), dim3(64), 0, st, info,
@@ -220,8 +244,8 @@ struct Run {
       Pass d;
       d.nq = s; d.f = xb(1); d.ldf = ldx;
       d.gram = true;
-      if (one) { d.gb0 = s; d.gbn = s; }      // [Q_0 X_1]^T X_1
-      else { d.gb0 = s; d.gbn = s; }          // Q_0^T X_1 (rows [0,s) used)
+      d.gb0 = s; d.gbn = s;                   // [Q_0 X_1]^T X_1
+      d.needed = one ? 2 * s * s : s * s;     // P-2S needs Q_0^T X_1 only
       pass(d);
       epi(one ? EPI_P1S_INIT : EPI_S_ONLY, 1, false, false);
     }
@@ -236,6 +260,7 @@ struct Run {
         if (has_e) { d.e = xb(j + 1); d.lde = ldx; }
         d.gram = true; d.gb0 = j * s; d.gbn = has_e ? 2 * s : s;
         d.skip_eu = has_e;
+        d.needed = (int64_t)(j + 1) * s * d.gbn + (has_e ? s * s : 0);
         pass(d);
         epi(EPI_ONE_SYNC, j, has_e, true);
       } else {
@@ -250,6 +275,7 @@ struct Run {
         if (has_e) { d.e = xb(j + 1); d.lde = ldx; }
         d.gram = true; d.gb0 = j * s; d.gbn = has_e ? 2 * s : s;
         d.skip_eu = has_e;
+        d.needed = (int64_t)(j + 1) * s * d.gbn;
         pass(d);
         epi(EPI_ONE_SYNC, j, has_e, false);
       }
@@ -265,6 +291,7 @@ struct Run {
       Pass a1;                        // S = Q^T X_j
       a1.nq = j * s; a1.f = xb(j); a1.ldf = ldx;
       a1.gram = true; a1.gb0 = j * s; a1.gbn = s;
+      a1.needed = (int64_t)j * s * s;
       pass(a1);
       epi(EPI_S_ONLY, j, false, false);
       Pass a2;                        // V = X_j - Q S
@@ -275,6 +302,7 @@ struct Run {
       Pass a3;                        // Y = Q^T U_j
       a3.nq = j * s; a3.f = qb(j); a3.ldf = ldq;
       a3.gram = true; a3.gb0 = j * s; a3.gbn = s;
+      a3.needed = (int64_t)j * s * s;
       pass(a3);
       epi(EPI_Y_ONLY, j, false, false);
       Pass a4;                        // W = U_j - Q Y

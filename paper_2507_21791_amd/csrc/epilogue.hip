@@ -209,7 +209,9 @@ __global__ __launch_bounds__(kThreads) void epilogue_kernel(EpiArgs a) {
 }
 
 hipError_t launch_epilogue(const EpiArgs& a, hipStream_t st) {
+  prof_begin(BCGS_KERNEL_EPILOGUE, a.mode, 0.0, 0.0);
   hipLaunchKernelGGL(epilogue_kernel, dim3(1), dim3(kThreads), 0, st, a);
+  prof_end();
   return hipGetLastError();
 }
 
@@ -225,8 +227,10 @@ __global__ void fill_kernel(double* p, int64_t rows, int64_t cols, int64_t ld,
 hipError_t launch_fill(double* p, int64_t rows, int64_t cols, int64_t ld,
                        double value, hipStream_t st) {
   if (rows <= 0 || cols <= 0) return hipSuccess;
+  prof_begin(BCGS_KERNEL_OTHER, 0, 8.0 * rows * cols, 0.0);
   hipLaunchKernelGGL(fill_kernel, dim3((unsigned)cdiv(rows * cols, 256)),
                      dim3(256), 0, st, p, rows, cols, ld, value);
+  prof_end();
   return hipGetLastError();
 }
 

@@ -226,8 +226,11 @@ __global__ __launch_bounds__(kThreads) void gram_reduce_kernel(
 hipError_t launch_gram_reduce(const double* partial, int G, int64_t elems,
                               double* out, hipStream_t st) {
   const int64_t blocks = cdiv(elems, 64);
+  prof_begin(BCGS_KERNEL_REDUCE, 0, 8.0 * elems * (G + 1),
+             (double)elems * G);
   hipLaunchKernelGGL(gram_reduce_kernel, dim3((unsigned)blocks),
                      dim3(kThreads), 0, st, partial, G, elems, out);
+  prof_end();
   return hipGetLastError();
 }
 
@@ -241,7 +244,9 @@ size_t pass_lds_bytes(const PassArgs<T>& a) {
 }
 
 template <typename T, bool GRAM, int NTB, int MAXA>
-static hipError_t launch_one(const PassArgs<T>& a, int G, hipStream_t st) {
+static hipError_t launch_one(const PassArgs<T>& a, int G, hipStream_t st,
+                             int* tag) {
+  *tag = (GRAM ? 100 : 0) + 10 * NTB + MAXA;
   auto kern = pass_kernel<T, GRAM, NTB, MAXA>;
   const size_t lds = pass_lds_bytes(a);
   static bool attr_done = false;
@@ -257,13 +262,14 @@ static hipError_t launch_one(const PassArgs<T>& a, int G, hipStream_t st) {
 }
 
 template <typename T>
-hipError_t launch_pass(const PassArgs<T>& a, int G, hipStream_t st) {
-  if (!a.gram) return launch_one<T, false, 1, 1>(a, G, st);
+hipError_t launch_pass(const PassArgs<T>& a, int G, hipStream_t st,
+                       int* tag) {
+  if (!a.gram) return launch_one<T, false, 1, 1>(a, G, st, tag);
   const int ntb = a.gbn_p / 16;
   const int maxa = (a.a_blocks_per_group + kWaves - 1) / kWaves;
 #define BCGS_TRY(NTB_, MAXA_)                                  \
   if (ntb == NTB_ && maxa <= MAXA_)                            \
-    return launch_one<T, true, NTB_, MAXA_>(a, G, st);
+    return launch_one<T, true, NTB_, MAXA_>(a, G, st, tag);
   BCGS_TRY(1, 1) BCGS_TRY(1, 2) BCGS_TRY(1, 4) BCGS_TRY(1, 8)
   BCGS_TRY(2, 1) BCGS_TRY(2, 2) BCGS_TRY(2, 4) BCGS_TRY(2, 8)
   BCGS_TRY(4, 1) BCGS_TRY(4, 2) BCGS_TRY(4, 4)
@@ -273,7 +279,7 @@ hipError_t launch_pass(const PassArgs<T>& a, int G, hipStream_t st) {
 }
 
 template hipError_t launch_pass<double>(const PassArgs<double>&, int,
-                                        hipStream_t);
+                                        hipStream_t, int*);
 template size_t pass_lds_bytes<double>(const PassArgs<double>&);
 
 }  // namespace bcgs

@@ -321,25 +321,39 @@ hipError_t launch_tsqr(const TsqrPlan& tp, const T* v, int64_t ldv, T* dst,
     once = true;
   }
   const int s = tp.s, cr = tp.cr, fan = tp.fan;
+  const double ss = (double)s * s, esz = sizeof(T);
+  // algorithmic work: Householder QR of the m x s block (2 m s^2) and the
+  // formation of its explicit Q (2 m s^2); the tree is O(nchunks s^3)
+  prof_begin(BCGS_KERNEL_TSQR_LEAF, 0, esz * m * s, 2.0 * m * ss);
   hipLaunchKernelGGL(tsqr_leaf_kernel<T>, dim3((unsigned)tp.nchunks),
                      dim3(kThreads), tsqr_lds_bytes(cr, s, false), st, v, ldv,
                      m, cr, s, ws + tp.r_off[0]);
+  prof_end();
   for (int l = 1; l <= tp.levels; ++l) {
+    const double rows = (double)tp.nodes[l - 1] * s;
+    prof_begin(BCGS_KERNEL_TSQR_NODE, l, 8.0 * rows * s * 2,
+               4.0 * rows * ss);
     hipLaunchKernelGGL(tsqr_node_kernel, dim3((unsigned)tp.nodes[l]),
                        dim3(kThreads), tsqr_lds_bytes(fan * s, s, true), st,
                        ws + tp.r_off[l - 1], tp.nodes[l - 1], fan, s,
                        ws + tp.r_off[l], ws + tp.q_off[l],
                        l == tp.levels ? 1 : 0, r_out, r_rs, r_cs);
+    prof_end();
   }
   for (int l = tp.levels; l >= 1; --l) {
+    const double n = (double)tp.nodes[l - 1];
+    prof_begin(BCGS_KERNEL_TSQR_DOWN, l, 8.0 * n * ss * 2, 2.0 * n * ss * s);
     hipLaunchKernelGGL(tsqr_down_kernel, dim3((unsigned)tp.nodes[l - 1]),
                        dim3(kThreads), 0, st, ws + tp.q_off[l],
                        ws + tp.c_off[l], tp.nodes[l - 1], fan, s,
                        ws + tp.c_off[l - 1], l == tp.levels ? 1 : 0);
+    prof_end();
   }
+  prof_begin(BCGS_KERNEL_TSQR_APPLY, 0, 2.0 * esz * m * s, 2.0 * m * ss);
   hipLaunchKernelGGL(tsqr_apply_kernel<T>, dim3((unsigned)tp.nchunks),
                      dim3(kThreads), tsqr_lds_bytes(cr, s, true), st, v, ldv,
                      m, cr, s, ws + tp.c_off[0], dst, ldd);
+  prof_end();
   return hipGetLastError();
 }
 
