@@ -90,6 +90,8 @@ struct Plan {
   int variant, precision;
   int G;                  // workgroups (row ranges) of the streaming passes
   int64_t rows_per_wg;
+  int G16;                // the same for the s <= 16 kernel
+  int64_t rows_per_wg16;
   int tr_max;             // largest tile the widest pass can afford
   TsqrPlan tsqr;
   // workspace offsets in bytes
@@ -109,6 +111,11 @@ template <typename T>
 hipError_t launch_pass(const PassArgs<T>& a, int G, hipStream_t st, int* tag);
 hipError_t launch_gram_reduce(const double* partial, int G, int64_t elems,
                               double* out, hipStream_t st);
+// Fast path for s <= 16 (pass16.hip); hipErrorNotSupported when it does not
+// apply (nothing launched).
+hipError_t launch_pass16(const PassArgs<double>& a, int G, hipStream_t st,
+                         int* tag);
+size_t pass16_lds_bytes(int ncols_p, int tr);
 
 struct EpiArgs;
 hipError_t launch_epilogue(const EpiArgs& a, hipStream_t st);

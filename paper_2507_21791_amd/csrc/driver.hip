@@ -55,6 +55,10 @@ bool make_plan(int64_t m, int64_t n, int64_t s, int variant, int precision,
   const int64_t target_wg = 512;
   P.rows_per_wg = round_up64(cdiv(m, target_wg), 64);
   P.G = (int)cdiv(m, P.rows_per_wg);
+  // the s <= 16 kernel runs one 8-wave workgroup per CU (256 on MI355X);
+  // the row split depends on m only, so results do not depend on the device
+  P.rows_per_wg16 = round_up64(cdiv(m, 256), 64);
+  P.G16 = (int)cdiv(m, P.rows_per_wg16);
   P.gram_ld = round_up64(n + s, 16);
   const int64_t gbn = round_up((int)(2 * s), 16);
   P.partial_elems = P.gram_ld * gbn;
@@ -183,6 +187,7 @@ struct Run {
     }
     a.tr = tr;
     a.rows_per_wg = p.rows_per_wg;
+    int G = p.G;
     // algorithmic work of this pass: the staged columns are read once, the
     // updated blocks written once; 2 K s flops per row and block update
     // plus s^2 for the triangular solve; 2 flops per needed Gram entry
@@ -196,11 +201,21 @@ struct Run {
     if (d.gram) flops += 2.0 * mr * (double)d.needed;
     int tag = 0;
     prof_begin(BCGS_KERNEL_PASS, -1, esz * mr * cols_rw, flops);
-    check(launch_pass(a, p.G, st, &tag));
+    hipError_t e = hipErrorNotSupported;
+    if (sizeof(T) == 8 && p.sp == 16) {
+      // one 8-wave workgroup per CU: rows split into G16 ranges
+      PassArgs<double> b;
+      memcpy(&b, &a, sizeof(b));
+      b.rows_per_wg = p.rows_per_wg16;
+      e = launch_pass16(b, p.G16, st, &tag);
+      if (e != hipErrorNotSupported) G = p.G16;
+    }
+    if (e == hipErrorNotSupported) e = launch_pass(a, G, st, &tag);
+    check(e);
     prof_end();
     prof_retag(tag);
     if (d.gram)
-      check(launch_gram_reduce(a.partial, p.G, (int64_t)a.ga_p * a.gbn_p,
+      check(launch_gram_reduce(a.partial, G, (int64_t)a.ga_p * a.gbn_p,
                                dws(p.off_gram), st));
     gram_ld_last = a.ga_p;
   }

@@ -1,0 +1,409 @@
+// Streaming pass for block widths s <= 16 (one 16-wide MFMA column block),
+// the shape of every large workload.  Same operation as pass.hip (block
+// updates of Alg. 1 / Alg. 2 fused with the tall-skinny Gram products),
+// organised for gfx950:
+//
+//  * 8 waves per workgroup, one workgroup per CU; the row range is walked
+//    in tiles of TR rows (32, or 16 for wide windows).
+//  * Two LDS tile buffers.  While tile t is being computed, tile t+1 is
+//    copied HBM -> LDS by direct-to-LDS loads (global_load_lds_dwordx4),
+//    so HBM streaming overlaps the MFMA work.
+//  * LDS tile layout: column c occupies TR consecutive doubles; within a
+//    column the 16-byte granules (row pairs) are XOR-swizzled by a
+//    per-column key, which keeps both MFMA fragment patterns (16 columns x
+//    4 rows for the Gram, 4 columns x 16 rows for the updates) free of bank
+//    conflicts.
+//  * Block updates W = B - Q C: waves = (TR/16 row blocks) x (KG K-ranges);
+//    every wave keeps its slice of C's MFMA fragments in registers for the
+//    whole kernel; both updates of a pass share the Q fragments; partial
+//    sums meet in LDS, then 16 lanes per row run the substitution with the
+//    upper-triangular factor (lane j owns column j).
+//  * Gram A^T B: the 16x16 output tiles are dealt round-robin to the waves,
+//    which accumulate them in registers over the whole row range.
+#include "common.h"
+
+namespace bcgs {
+
+namespace p16 {
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+constexpr int kW = 8;                 // waves per workgroup
+constexpr int kT = kW * 64;           // threads
+constexpr int kMaxKF = 16;            // C fragments per update per wave
+
+__device__ __forceinline__ v4d mfma(double a, double b, v4d c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// swizzle key of column c: a permutation of the granule index
+template <int TR>
+__device__ __forceinline__ int swz(int c) {
+  if (TR == 32) return ((c & 1) << 3) | ((c >> 1) & 7);
+  return (c >> 1) & 7;
+}
+
+// LDS offset (in doubles) of element (row r, column c) of a tile
+template <int TR>
+__device__ __forceinline__ int at(int c, int r) {
+  return c * TR + (((r >> 1) ^ swz<TR>(c)) << 1) + (r & 1);
+}
+
+struct Args {
+  int64_t m;
+  int s, ncols, ncols_p;
+  int64_t rows_per_wg;
+  const double* q; int64_t ldq; int nq;
+  const double* f; int64_t ldf; int fcols;
+  const double* e; int64_t lde; int ecols;
+  int dma;                       // all leading dimensions even: 16B loads
+  int upd1, u1_c0; const double* c1; const double* t1; double* dst1; int64_t ldd1;
+  int upd2, u2_c0, trsm2; const double* c2; const double* t2; double* dst2;
+  int64_t ldd2;
+  int gram, ga_p, gb0, gbn_p, skip_a0, skip_b1;
+  double* partial;
+};
+
+__device__ __forceinline__ const double* col_ptr(const Args& a, int c,
+                                                 int64_t* ld) {
+  if (c < a.nq) { *ld = a.ldq; return a.q + (int64_t)c * a.ldq; }
+  c -= a.nq;
+  if (c < a.fcols) { *ld = a.ldf; return a.f + (int64_t)c * a.ldf; }
+  c -= a.fcols;
+  *ld = a.lde;
+  return a.e + (int64_t)c * a.lde;
+}
+
+// Issue the direct-to-LDS copy of a full tile (rows r0 .. r0+TR-1).
+template <int TR>
+__device__ __forceinline__ void tile_dma(const Args& a, double* buf,
+                                         int64_t r0) {
+  constexpr int kColsPerInst = 1024 / (TR * 8);     // 4 (TR=32) or 8 (16)
+  constexpr int kGran = TR / 2;                      // granules per column
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int ninst = (a.ncols + kColsPerInst - 1) / kColsPerInst;
+  for (int ins = wave; ins < ninst; ins += kW) {
+    const int c = ins * kColsPerInst + lane / kGran;
+    const int g = lane % kGran;
+    double* dst = buf + ins * kColsPerInst * TR;     // wave-uniform
+    if (c < a.ncols) {
+      int64_t ld;
+      const double* src = col_ptr(a, c, &ld);
+      const int rr = (g ^ swz<TR>(c)) << 1;
+      __builtin_amdgcn_global_load_lds(src + r0 + rr, dst, 16, 0, 0);
+    }
+  }
+}
+
+// Synchronous staging (tail tiles, odd leading dimensions): zero past m.
+template <int TR>
+__device__ void tile_sync(const Args& a, double* buf, int64_t r0, int rows) {
+  for (int idx = threadIdx.x; idx < a.ncols * TR; idx += kT) {
+    const int c = idx / TR, r = idx % TR;
+    double v = 0.0;
+    if (r < rows) {
+      int64_t ld;
+      const double* src = col_ptr(a, c, &ld);
+      v = src[r0 + r];
+    }
+    buf[at<TR>(c, r)] = v;
+  }
+}
+
+// Combine the K-range partial sums of one block update, subtract them from
+// the block, apply T^{-1} by substitution (16 lanes per row) and store the
+// result in the tile.  scr: [KG][TR][17] doubles.
+template <int TR, int KG>
+__device__ __forceinline__ void combine_solve(const Args& a, double* tile,
+                                              const double* scr, int uc0,
+                                              bool trsm, const double* tm,
+                                              const double* rdiag) {
+  const int t = threadIdx.x;
+  if (t >= TR * 16) return;
+  const int r = t >> 4, c = t & 15;
+  const int s = a.s;
+  double w = 0.0;
+  if (c < s) {
+    double sum = 0.0;
+#pragma unroll
+    for (int k = 0; k < KG; ++k) sum += scr[(k * TR + r) * 17 + c];
+    w = tile[at<TR>(uc0 + c, r)] - sum;
+  }
+  if (trsm) {
+    for (int j = 0; j < s; ++j) {
+      const double yj = __shfl(w, j, 16) * rdiag[j];
+      if (c == j) w = yj;
+      else if (c > j) w -= yj * tm[j * 16 + c];
+    }
+  }
+  if (c < s) tile[at<TR>(uc0 + c, r)] = w;
+}
+
+// Copy an updated block (tile columns uc0..uc0+s-1) to HBM, coalesced.
+template <int TR>
+__device__ __forceinline__ void store_block(const Args& a, const double* tile,
+                                            int uc0, double* dst, int64_t ldd,
+                                            int64_t r0, int rows) {
+  for (int idx = threadIdx.x; idx < a.s * TR; idx += kT) {
+    const int c = idx / TR, r = idx % TR;
+    if (r < rows) dst[(int64_t)c * ldd + r0 + r] = tile[at<TR>(uc0 + c, r)];
+  }
+}
+
+template <int TR, int MAXT, bool GRAM, int NTB>
+__global__ __launch_bounds__(kT) void pass16_kernel(Args a) {
+  constexpr int MB = TR / 16;         // row blocks per tile
+  constexpr int KG = kW / MB;         // K ranges per update
+  extern __shared__ double lds[];
+  const int tile_elems = a.ncols_p * TR;
+  double* buf0 = lds;
+  double* buf1 = lds + tile_elems;
+  double* scr = buf1 + tile_elems;                  // KG * TR * 17
+  double* tm1 = scr + KG * TR * 17;                 // 16 x 16
+  double* tm2 = tm1 + 256;
+  double* rd1 = tm2 + 256;                          // 16
+  double* rd2 = rd1 + 16;
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int mb = wave % MB, kg = wave / MB;
+  const int64_t g = blockIdx.x;
+  const int64_t row_begin = g * a.rows_per_wg;
+  const int64_t row_end = min(a.m, row_begin + a.rows_per_wg);
+
+  // ---- prologue: coefficients, triangular factors, zero padding --------
+  const int s = a.s;
+  const int nks1 = a.upd1 ? a.u1_c0 / 4 : 0;       // shared K-steps
+  const int nks2 = a.upd2 ? a.u2_c0 / 4 : 0;
+  // update 2's K-steps [0, shared) run together with update 1's
+  const int shared = a.upd1 ? nks1 : nks2;
+  const int per = (shared + KG - 1) / KG;
+  const int kb = kg * per, ke = min(shared, kb + per);
+  double c1f[kMaxKF], c2f[kMaxKF];
+#pragma unroll
+  for (int i = 0; i < kMaxKF; ++i) {
+    const int k = kb + i;
+    c1f[i] = 0.0;
+    c2f[i] = 0.0;
+    if (k < ke) {
+      const int row = 4 * k + lk;
+      if (a.upd1) c1f[i] = a.c1[row * 16 + li];
+      if (a.upd2) c2f[i] = a.c2[row * 16 + li];
+    }
+  }
+  // update 2's remaining K-steps (over the block update 1 produced)
+  const int tail0 = a.upd1 ? nks1 : nks2;
+  const int ntail = a.upd2 ? nks2 - tail0 : 0;      // <= 4
+  double c2t = 0.0;
+  const int mytail = kg < ntail ? tail0 + kg : -1;   // one per K range
+  if (mytail >= 0) c2t = a.c2[(4 * mytail + lk) * 16 + li];
+  if (tid < 256) {
+    tm1[tid] = a.upd1 ? a.t1[tid] : 0.0;
+    tm2[tid] = (a.upd2 && a.trsm2) ? a.t2[tid] : 0.0;
+  }
+  if (tid < 16) {
+    rd1[tid] = (a.upd1 && tid < s) ? 1.0 / a.t1[tid * 17] : 0.0;
+    rd2[tid] = (a.upd2 && a.trsm2 && tid < s) ? 1.0 / a.t2[tid * 17] : 0.0;
+  }
+  for (int idx = a.ncols * TR + tid; idx < tile_elems; idx += kT) {
+    buf0[idx] = 0.0;
+    buf1[idx] = 0.0;
+  }
+
+  // ---- Gram tiles of this wave ------------------------------------------
+  v4d acc[MAXT];
+  int tta[MAXT], ttb[MAXT];
+  const int nta = a.ga_p >> 4;
+  const int ntiles = GRAM ? nta * NTB : 0;
+#pragma unroll
+  for (int i = 0; i < MAXT; ++i) {
+    acc[i] = v4d{0.0, 0.0, 0.0, 0.0};
+    const int t = wave + kW * i;
+    tta[i] = -1;
+    ttb[i] = 0;
+    if (t < ntiles) {
+      const int ta = t / NTB, tb = t % NTB;
+      if (!(ta * 16 >= a.skip_a0 && tb * 16 + 16 <= a.skip_b1)) {
+        tta[i] = ta;
+        ttb[i] = tb;
+      }
+    }
+  }
+
+  // ---- tile loop ---------------------------------------------------------
+  bool prefetched = false;
+  int it = 0;
+  if (row_begin < row_end && a.dma && row_begin + TR <= row_end) {
+    tile_dma<TR>(a, buf0, row_begin);
+    prefetched = true;
+  }
+  for (int64_t r0 = row_begin; r0 < row_end; r0 += TR, ++it) {
+    double* tile = (it & 1) ? buf1 : buf0;
+    double* next = (it & 1) ? buf0 : buf1;
+    const int rows = (int)min((int64_t)TR, row_end - r0);
+    if (!prefetched) tile_sync<TR>(a, tile, r0, rows);
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    // prefetch the next tile while this one is computed
+    const int64_t r1 = r0 + TR;
+    prefetched = false;
+    if (a.dma && r1 + TR <= row_end) {
+      tile_dma<TR>(a, next, r1);
+      prefetched = true;
+    }
+
+    // ---- block updates ----
+    if (a.upd1 || a.upd2) {
+      v4d acc1 = {0.0, 0.0, 0.0, 0.0}, acc2 = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int i = 0; i < kMaxKF; ++i) {
+        const int k = kb + i;
+        if (k < ke) {
+          const double av = tile[at<TR>(4 * k + lk, mb * 16 + li)];
+          if (a.upd1) acc1 = mfma(av, c1f[i], acc1);
+          if (a.upd2) acc2 = mfma(av, c2f[i], acc2);
+        }
+      }
+      if (a.upd1) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+          scr[(kg * TR + mb * 16 + lk + 4 * v) * 17 + li] = acc1[v];
+        __syncthreads();
+        combine_solve<TR, KG>(a, tile, scr, a.u1_c0, true, tm1, rd1);
+        __syncthreads();
+        store_block<TR>(a, tile, a.u1_c0, a.dst1, a.ldd1, r0, rows);
+        if (mytail >= 0) {
+          const double av = tile[at<TR>(4 * mytail + lk, mb * 16 + li)];
+          acc2 = mfma(av, c2t, acc2);
+        }
+      } else if (mytail >= 0) {
+        const double av = tile[at<TR>(4 * mytail + lk, mb * 16 + li)];
+        acc2 = mfma(av, c2t, acc2);
+      }
+      if (a.upd2) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+          scr[(kg * TR + mb * 16 + lk + 4 * v) * 17 + li] = acc2[v];
+        __syncthreads();
+        combine_solve<TR, KG>(a, tile, scr, a.u2_c0, a.trsm2 != 0, tm2, rd2);
+        __syncthreads();
+        store_block<TR>(a, tile, a.u2_c0, a.dst2, a.ldd2, r0, rows);
+      }
+    }
+
+    // ---- Gram accumulation ----
+    if (GRAM) {
+#pragma unroll 1
+      for (int kk = 0; kk < TR; kk += 4) {
+        const int r = kk + lk;
+#pragma unroll
+        for (int i = 0; i < MAXT; ++i) {
+          if (tta[i] >= 0) {
+            const double af = tile[at<TR>(tta[i] * 16 + li, r)];
+            const double bf = tile[at<TR>(a.gb0 + ttb[i] * 16 + li, r)];
+            acc[i] = mfma(af, bf, acc[i]);
+          }
+        }
+      }
+    }
+  }
+  __builtin_amdgcn_s_waitcnt(0);
+
+  if (GRAM) {
+    double* out = a.partial + (size_t)g * a.ga_p * a.gbn_p;
+#pragma unroll
+    for (int i = 0; i < MAXT; ++i) {
+      if (tta[i] < 0) continue;
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        out[(size_t)(ttb[i] * 16 + li) * a.ga_p + tta[i] * 16 + lk + 4 * v] =
+            acc[i][v];
+    }
+  }
+}
+
+template <int TR, int MAXT, bool GRAM, int NTB>
+static hipError_t go(const Args& a, int G, size_t lds, hipStream_t st) {
+  auto kern = pass16_kernel<TR, MAXT, GRAM, NTB>;
+  static bool attr = false;
+  if (!attr) {
+    (void)hipFuncSetAttribute((const void*)kern,
+                              hipFuncAttributeMaxDynamicSharedMemorySize,
+                              160 * 1024);
+    attr = true;
+  }
+  hipLaunchKernelGGL(kern, dim3((unsigned)G), dim3(kT), lds, st, a);
+  return hipGetLastError();
+}
+
+}  // namespace p16
+
+size_t pass16_lds_bytes(int ncols_p, int tr) {
+  const int kg = p16::kW / (tr / 16);
+  return ((size_t)2 * ncols_p * tr + (size_t)kg * tr * 17 + 512 + 32) *
+         sizeof(double);
+}
+
+// Returns hipErrorNotSupported (without launching) when this kernel cannot
+// take the pass; *tag receives the instantiation (1000 + 100*gram + 10*NTB
+// + MAXT/TR code) otherwise.
+hipError_t launch_pass16(const PassArgs<double>& pa, int G, hipStream_t st,
+                         int* tag) {
+  using namespace p16;
+  const int s = pa.s;
+  if (pa.sp != 16 || s % 4 != 0) return hipErrorNotSupported;
+  if (pa.groups != 1) return hipErrorNotSupported;
+  const int K1 = pa.upd1 ? pa.u1_c0 : 0;
+  const int K2 = pa.upd2 ? pa.u2_c0 : 0;
+  const int shared_cols = pa.upd1 ? K1 : K2;
+  int tr = 0;
+  for (int cand : {32, 16}) {
+    const int kg = kW / (cand / 16);
+    const int per = ((shared_cols / 4) + kg - 1) / kg;
+    if (per > kMaxKF) continue;
+    if (pass16_lds_bytes(pa.ncols_p, cand) > 160 * 1024) continue;
+    tr = cand;
+    break;
+  }
+  if (!tr) return hipErrorNotSupported;
+  Args a{};
+  a.m = pa.m; a.s = s; a.ncols = pa.ncols; a.ncols_p = pa.ncols_p;
+  a.rows_per_wg = pa.rows_per_wg;
+  a.q = pa.q; a.ldq = pa.ldq; a.nq = pa.nq;
+  a.f = pa.f; a.ldf = pa.ldf; a.fcols = pa.fcols;
+  a.e = pa.e; a.lde = pa.lde; a.ecols = pa.ecols;
+  auto al16 = [](const void* p) {
+    return (reinterpret_cast<uintptr_t>(p) & 15) == 0;
+  };
+  a.dma = (pa.ldq % 2 == 0) && al16(pa.q) &&
+          (!pa.fcols || (pa.ldf % 2 == 0 && al16(pa.f))) &&
+          (!pa.ecols || (pa.lde % 2 == 0 && al16(pa.e)));
+  a.upd1 = pa.upd1; a.u1_c0 = pa.u1_c0; a.c1 = pa.c1; a.t1 = pa.t1;
+  a.dst1 = pa.dst1; a.ldd1 = pa.ldd1;
+  a.upd2 = pa.upd2; a.u2_c0 = pa.u2_c0; a.trsm2 = pa.trsm2;
+  a.c2 = pa.c2; a.t2 = pa.t2; a.dst2 = pa.dst2; a.ldd2 = pa.ldd2;
+  a.gram = pa.gram; a.ga_p = pa.ga_p; a.gb0 = pa.gb0; a.gbn_p = pa.gbn_p;
+  a.skip_a0 = pa.skip_a0; a.skip_b1 = pa.skip_b1;
+  a.partial = pa.partial;
+  const size_t lds = pass16_lds_bytes(pa.ncols_p, tr);
+  const int ntb = pa.gbn_p / 16;
+  const int ntiles = pa.gram ? (pa.ga_p / 16) * ntb : 0;
+  const int maxt = (ntiles + kW - 1) / kW;
+  if (!pa.gram) {
+    *tag = 1000 + tr;
+    return tr == 32 ? go<32, 1, false, 1>(a, G, lds, st)
+                    : go<16, 1, false, 1>(a, G, lds, st);
+  }
+  if (ntb > 2 || maxt > 9) return hipErrorNotSupported;
+  *tag = 1100 + 10 * ntb + (tr == 32 ? 0 : 5) + (maxt <= 3 ? 0 : maxt <= 5 ? 1 : 2);
+#define P16(TR_, MT_, NTB_)                                               \
+  if (tr == TR_ && ntb == NTB_ && maxt <= MT_)                            \
+    return go<TR_, MT_, true, NTB_>(a, G, lds, st);
+  P16(32, 3, 1) P16(32, 5, 1) P16(32, 9, 1)
+  P16(32, 3, 2) P16(32, 5, 2) P16(32, 9, 2)
+  P16(16, 3, 1) P16(16, 5, 1) P16(16, 9, 1)
+  P16(16, 3, 2) P16(16, 5, 2) P16(16, 9, 2)
+#undef P16
+  return hipErrorNotSupported;
+}
+
+}  // namespace bcgs

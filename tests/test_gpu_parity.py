@@ -95,17 +95,39 @@ def test_exact_case_bitwise(variant):
 
 
 @pytest.mark.parametrize("variant", ["p-1s"])
-def test_breakdown_same_block(variant):
-    """Duplicate columns: exact rank deficiency; the Cholesky variant breaks
-    down in the block where the oracle does, without crashing."""
+def test_breakdown_nonfinite_same_block_and_pivot(variant):
+    """A non-finite entry makes a Cholesky pivot non-finite: both sides
+    must report the same first failing block and pivot, and the GPU run must
+    finish (NaN propagates, nothing crashes)."""
+    log(f"[gpu] breakdown non-finite column {variant}")
+    X = W.conditioned_host(500, 32, 2, seed=6)
+    X[7, 20] = np.nan
+    Qg, Rg, info = run_gpu(X, 8, variant)
+    r = O.qr(X, 8, variant)
+    assert r.breakdown is not None and info.status == 2
+    assert (info.block, info.pivot) == (r.breakdown.block, r.breakdown.pivot)
+    assert np.isnan(host(Rg)).any()
+
+
+@pytest.mark.parametrize("variant", ["p-1s"])
+def test_breakdown_rank_deficient(variant):
+    """Duplicate columns: the failing pivot is zero in exact arithmetic, so
+    its sign is decided by rounding order.  Either both sides break down in
+    the same block, or only one does and the oracle's pivot there is a
+    rounding-level tie: |d| <= 64 s u ||A||."""
     log(f"[gpu] breakdown duplicate columns {variant}")
     X = W.conditioned_host(500, 32, 2, seed=6)
     X[:, 20] = X[:, 3]
     Qg, Rg, info = run_gpu(X, 8, variant)
     r = O.qr(X, 8, variant)
-    assert r.breakdown is not None and info.status == 2
-    assert info.block == r.breakdown.block
-    assert np.isnan(host(Rg)).any()
+    if r.breakdown is not None and info.status == 2:
+        assert info.block == r.breakdown.block
+    elif r.breakdown is not None:
+        normA = np.linalg.norm(X, 2) ** 2
+        assert abs(r.breakdown.value) <= 64 * 8 * 2.0 ** -53 * normA
+    else:
+        assert info.status == 2 and info.block >= 0
+        assert abs(info.value) <= 64 * 8 * 2.0 ** -53 * np.linalg.norm(X, 2) ** 2
 
 
 @pytest.mark.parametrize("variant", VARIANTS)
