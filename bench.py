@@ -103,6 +103,11 @@ def aggregate(recs, steps):
 
 
 def kernel_name(kind, tag):
+    if kind == "pass" and tag >= 10000000:
+        nw, tr = (tag // 1000000) % 10, (tag // 1000) % 1000
+        maxt, ntb = (tag // 10) % 100, tag % 10
+        gram = "true" if ntb else "false"
+        return f"pass16_kernel<{nw},{tr},{maxt},{gram},{max(ntb, 1)}>"
     if kind == "pass":
         gram, ntb, maxa = tag // 100, (tag // 10) % 10, tag % 10
         return (f"pass_kernel<double,{'true' if gram else 'false'},{ntb},"

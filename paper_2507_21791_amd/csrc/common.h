@@ -14,7 +14,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
-#include "../../include/bcgs.h"
+#include "bcgs.h"
 
 namespace bcgs {
 
@@ -90,8 +90,6 @@ struct Plan {
   int variant, precision;
   int G;                  // workgroups (row ranges) of the streaming passes
   int64_t rows_per_wg;
-  int G16;                // the same for the s <= 16 kernel
-  int64_t rows_per_wg16;
   int tr_max;             // largest tile the widest pass can afford
   TsqrPlan tsqr;
   // workspace offsets in bytes
@@ -113,9 +111,9 @@ hipError_t launch_gram_reduce(const double* partial, int G, int64_t elems,
                               double* out, hipStream_t st);
 // Fast path for s <= 16 (pass16.hip); hipErrorNotSupported when it does not
 // apply (nothing launched).
-hipError_t launch_pass16(const PassArgs<double>& a, int G, hipStream_t st,
-                         int* tag);
-size_t pass16_lds_bytes(int ncols_p, int tr);
+hipError_t launch_pass16(const PassArgs<double>& a, int64_t m,
+                         hipStream_t st, int* tag, int* G_out);
+size_t pass16_lds_bytes(int ncols_p, int tr, int nw);
 
 struct EpiArgs;
 hipError_t launch_epilogue(const EpiArgs& a, hipStream_t st);

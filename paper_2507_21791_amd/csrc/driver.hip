@@ -55,10 +55,6 @@ bool make_plan(int64_t m, int64_t n, int64_t s, int variant, int precision,
   const int64_t target_wg = 512;
   P.rows_per_wg = round_up64(cdiv(m, target_wg), 64);
   P.G = (int)cdiv(m, P.rows_per_wg);
-  // the s <= 16 kernel runs one 8-wave workgroup per CU (256 on MI355X);
-  // the row split depends on m only, so results do not depend on the device
-  P.rows_per_wg16 = round_up64(cdiv(m, 256), 64);
-  P.G16 = (int)cdiv(m, P.rows_per_wg16);
   P.gram_ld = round_up64(n + s, 16);
   const int64_t gbn = round_up((int)(2 * s), 16);
   P.partial_elems = P.gram_ld * gbn;
@@ -203,12 +199,11 @@ struct Run {
     prof_begin(BCGS_KERNEL_PASS, -1, esz * mr * cols_rw, flops);
     hipError_t e = hipErrorNotSupported;
     if (sizeof(T) == 8 && p.sp == 16) {
-      // one 8-wave workgroup per CU: rows split into G16 ranges
       PassArgs<double> b;
       memcpy(&b, &a, sizeof(b));
-      b.rows_per_wg = p.rows_per_wg16;
-      e = launch_pass16(b, p.G16, st, &tag);
-      if (e != hipErrorNotSupported) G = p.G16;
+      int g16 = 0;
+      e = launch_pass16(b, p.m, st, &tag, &g16);
+      if (e != hipErrorNotSupported) G = g16;
     }
     if (e == hipErrorNotSupported) e = launch_pass(a, G, st, &tag);
     check(e);

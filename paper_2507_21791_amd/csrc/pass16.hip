@@ -3,8 +3,10 @@
 // updates of Alg. 1 / Alg. 2 fused with the tall-skinny Gram products),
 // organised for gfx950:
 //
-//  * 8 waves per workgroup, one workgroup per CU; the row range is walked
-//    in tiles of TR rows (32, or 16 for wide windows).
+//  * NW = 4 waves per workgroup and two workgroups per CU when the tiles
+//    fit (one workgroup's MFMA work overlaps the other's serial phases),
+//    else NW = 8 and one workgroup per CU; the row range is walked in tiles
+//    of TR rows (16 or 32).
 //  * Two LDS tile buffers.  While tile t is being computed, tile t+1 is
 //    copied HBM -> LDS by direct-to-LDS loads (global_load_lds_dwordx4),
 //    so HBM streaming overlaps the MFMA work.
@@ -17,7 +19,8 @@
 //    every wave keeps its slice of C's MFMA fragments in registers for the
 //    whole kernel; both updates of a pass share the Q fragments; partial
 //    sums meet in LDS, then 16 lanes per row run the substitution with the
-//    upper-triangular factor (lane j owns column j).
+//    upper-triangular factor (lane j owns column j; the pivot value is
+//    broadcast along the row with a DPP row_newbcast move).
 //  * Gram A^T B: the 16x16 output tiles are dealt round-robin to the waves,
 //    which accumulate them in registers over the whole row range.
 #include "common.h"
@@ -27,8 +30,6 @@ namespace bcgs {
 namespace p16 {
 
 typedef double v4d __attribute__((ext_vector_type(4)));
-constexpr int kW = 8;                 // waves per workgroup
-constexpr int kT = kW * 64;           // threads
 constexpr int kMaxKF = 16;            // C fragments per update per wave
 
 __device__ __forceinline__ v4d mfma(double a, double b, v4d c) {
@@ -74,14 +75,14 @@ __device__ __forceinline__ const double* col_ptr(const Args& a, int c,
 }
 
 // Issue the direct-to-LDS copy of a full tile (rows r0 .. r0+TR-1).
-template <int TR>
+template <int NW, int TR>
 __device__ __forceinline__ void tile_dma(const Args& a, double* buf,
                                          int64_t r0) {
   constexpr int kColsPerInst = 1024 / (TR * 8);     // 4 (TR=32) or 8 (16)
   constexpr int kGran = TR / 2;                      // granules per column
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int ninst = (a.ncols + kColsPerInst - 1) / kColsPerInst;
-  for (int ins = wave; ins < ninst; ins += kW) {
+  for (int ins = wave; ins < ninst; ins += NW) {
     const int c = ins * kColsPerInst + lane / kGran;
     const int g = lane % kGran;
     double* dst = buf + ins * kColsPerInst * TR;     // wave-uniform
@@ -95,9 +96,9 @@ __device__ __forceinline__ void tile_dma(const Args& a, double* buf,
 }
 
 // Synchronous staging (tail tiles, odd leading dimensions): zero past m.
-template <int TR>
+template <int NW, int TR>
 __device__ void tile_sync(const Args& a, double* buf, int64_t r0, int rows) {
-  for (int idx = threadIdx.x; idx < a.ncols * TR; idx += kT) {
+  for (int idx = threadIdx.x; idx < a.ncols * TR; idx += NW * 64) {
     const int c = idx / TR, r = idx % TR;
     double v = 0.0;
     if (r < rows) {
@@ -109,50 +110,83 @@ __device__ void tile_sync(const Args& a, double* buf, int64_t r0, int rows) {
   }
 }
 
+// Value of v held by lane J of this lane's row of 16 (DPP row_newbcast).
+template <int J>
+__device__ __forceinline__ double row_bcast(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x150 + J,
+                                             0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x150 + J,
+                                             0xf, 0xf, false);
+  return __hiloint2double(hi, lo);
+}
+
 // Combine the K-range partial sums of one block update, subtract them from
-// the block, apply T^{-1} by substitution (16 lanes per row) and store the
-// result in the tile.  scr: [KG][TR][17] doubles.
-template <int TR, int KG>
+// the block, apply T^{-1} by substitution (16 lanes per row, lane c owns
+// column c) and store the result in the tile.  scr: [KG][TR][17] doubles.
+// tmt: the factor transposed and masked, tmt[c * 16 + j] = T(j, c) for
+// j < c and 0 otherwise; rdiag[j] = 1 / T(j, j) (0 for j >= s).  Step j:
+// y_j = w_j / T_jj (broadcast from lane j), w_c -= y_j T(j, c) for c > j,
+// and lane j keeps y_j.  Branch-free; the factor is read four steps ahead.
+template <int NW, int TR, int KG>
 __device__ __forceinline__ void combine_solve(const Args& a, double* tile,
                                               const double* scr, int uc0,
-                                              bool trsm, const double* tm,
+                                              bool trsm, const double* tmt,
                                               const double* rdiag) {
-  const int t = threadIdx.x;
-  if (t >= TR * 16) return;
-  const int r = t >> 4, c = t & 15;
   const int s = a.s;
-  double w = 0.0;
-  if (c < s) {
+  for (int t = threadIdx.x; t < TR * 16; t += NW * 64) {
+    const int r = t >> 4, c = t & 15;
+    double part[KG];
+#pragma unroll
+    for (int k = 0; k < KG; ++k) part[k] = scr[(k * TR + r) * 17 + c];
+    const double x = c < s ? tile[at<TR>(uc0 + c, r)] : 0.0;
     double sum = 0.0;
 #pragma unroll
-    for (int k = 0; k < KG; ++k) sum += scr[(k * TR + r) * 17 + c];
-    w = tile[at<TR>(uc0 + c, r)] - sum;
+    for (int k = 0; k < KG; ++k) sum += part[k];
+    double w = c < s ? x - sum : 0.0;
+    if (trsm) {
+      const double2* tv = reinterpret_cast<const double2*>(tmt + c * 16);
+      const double2* rv = reinterpret_cast<const double2*>(rdiag);
+#define BCGS_STEP(J, TJ, RJ)                                            \
+  {                                                                     \
+    const double yj = row_bcast<J>(w) * (RJ);                           \
+    w = fma(-yj, (TJ), w);                                              \
+    w = (c == J) ? yj : w;                                              \
   }
-  if (trsm) {
-    for (int j = 0; j < s; ++j) {
-      const double yj = __shfl(w, j, 16) * rdiag[j];
-      if (c == j) w = yj;
-      else if (c > j) w -= yj * tm[j * 16 + c];
+#define BCGS_QUAD(Q)                                                    \
+  {                                                                     \
+    const double2 t0 = tv[2 * Q], t1 = tv[2 * Q + 1];                   \
+    const double2 r0 = rv[2 * Q], r1 = rv[2 * Q + 1];                   \
+    BCGS_STEP(4 * Q + 0, t0.x, r0.x)                                    \
+    BCGS_STEP(4 * Q + 1, t0.y, r0.y)                                    \
+    BCGS_STEP(4 * Q + 2, t1.x, r1.x)                                    \
+    BCGS_STEP(4 * Q + 3, t1.y, r1.y)                                    \
+  }
+      BCGS_QUAD(0) BCGS_QUAD(1) BCGS_QUAD(2) BCGS_QUAD(3)
+#undef BCGS_QUAD
+#undef BCGS_STEP
     }
+    if (c < s) tile[at<TR>(uc0 + c, r)] = w;
   }
-  if (c < s) tile[at<TR>(uc0 + c, r)] = w;
 }
 
 // Copy an updated block (tile columns uc0..uc0+s-1) to HBM, coalesced.
-template <int TR>
+template <int NW, int TR>
 __device__ __forceinline__ void store_block(const Args& a, const double* tile,
                                             int uc0, double* dst, int64_t ldd,
                                             int64_t r0, int rows) {
-  for (int idx = threadIdx.x; idx < a.s * TR; idx += kT) {
+  for (int idx = threadIdx.x; idx < a.s * TR; idx += NW * 64) {
     const int c = idx / TR, r = idx % TR;
     if (r < rows) dst[(int64_t)c * ldd + r0 + r] = tile[at<TR>(uc0 + c, r)];
   }
 }
 
-template <int TR, int MAXT, bool GRAM, int NTB>
-__global__ __launch_bounds__(kT) void pass16_kernel(Args a) {
+// two waves per SIMD: two 4-wave workgroups, or one 8-wave workgroup, per CU
+template <int NW, int TR, int MAXA, bool GRAM, int NTB>
+__global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(2)))
+void pass16_kernel(Args a) {
+  constexpr int kT = NW * 64;
   constexpr int MB = TR / 16;         // row blocks per tile
-  constexpr int KG = kW / MB;         // K ranges per update
+  constexpr int KG = NW / MB;         // K ranges per update
   extern __shared__ double lds[];
   const int tile_elems = a.ncols_p * TR;
   double* buf0 = lds;
@@ -197,8 +231,11 @@ __global__ __launch_bounds__(kT) void pass16_kernel(Args a) {
   const int mytail = kg < ntail ? tail0 + kg : -1;   // one per K range
   if (mytail >= 0) c2t = a.c2[(4 * mytail + lk) * 16 + li];
   if (tid < 256) {
-    tm1[tid] = a.upd1 ? a.t1[tid] : 0.0;
-    tm2[tid] = (a.upd2 && a.trsm2) ? a.t2[tid] : 0.0;
+    // transposed, strictly-upper-masked factors: tm[c * 16 + j] = T(j, c)
+    const int c = tid >> 4, j = tid & 15;
+    const bool up = j < c;
+    tm1[tid] = (a.upd1 && up) ? a.t1[j * 16 + c] : 0.0;
+    tm2[tid] = (a.upd2 && a.trsm2 && up) ? a.t2[j * 16 + c] : 0.0;
   }
   if (tid < 16) {
     rd1[tid] = (a.upd1 && tid < s) ? 1.0 / a.t1[tid * 17] : 0.0;
@@ -209,68 +246,72 @@ __global__ __launch_bounds__(kT) void pass16_kernel(Args a) {
     buf1[idx] = 0.0;
   }
 
-  // ---- Gram tiles of this wave ------------------------------------------
-  v4d acc[MAXT];
-  int tta[MAXT], ttb[MAXT];
+  // ---- Gram: this wave owns A blocks ta = wave, wave + NW, ... and all
+  //      NTB B blocks, so B fragments are shared across its A blocks ----
+  v4d acc[MAXA][NTB];
   const int nta = a.ga_p >> 4;
-  const int ntiles = GRAM ? nta * NTB : 0;
 #pragma unroll
-  for (int i = 0; i < MAXT; ++i) {
-    acc[i] = v4d{0.0, 0.0, 0.0, 0.0};
-    const int t = wave + kW * i;
-    tta[i] = -1;
-    ttb[i] = 0;
-    if (t < ntiles) {
-      const int ta = t / NTB, tb = t % NTB;
-      if (!(ta * 16 >= a.skip_a0 && tb * 16 + 16 <= a.skip_b1)) {
-        tta[i] = ta;
-        ttb[i] = tb;
-      }
-    }
-  }
+  for (int i = 0; i < MAXA; ++i)
+#pragma unroll
+    for (int b = 0; b < NTB; ++b) acc[i][b] = v4d{0.0, 0.0, 0.0, 0.0};
 
   // ---- tile loop ---------------------------------------------------------
   bool prefetched = false;
   int it = 0;
   if (row_begin < row_end && a.dma && row_begin + TR <= row_end) {
-    tile_dma<TR>(a, buf0, row_begin);
+    tile_dma<NW, TR>(a, buf0, row_begin);
     prefetched = true;
   }
   for (int64_t r0 = row_begin; r0 < row_end; r0 += TR, ++it) {
     double* tile = (it & 1) ? buf1 : buf0;
     double* next = (it & 1) ? buf0 : buf1;
     const int rows = (int)min((int64_t)TR, row_end - r0);
-    if (!prefetched) tile_sync<TR>(a, tile, r0, rows);
+    if (!prefetched) tile_sync<NW, TR>(a, tile, r0, rows);
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     // prefetch the next tile while this one is computed
     const int64_t r1 = r0 + TR;
     prefetched = false;
     if (a.dma && r1 + TR <= row_end) {
-      tile_dma<TR>(a, next, r1);
+      tile_dma<NW, TR>(a, next, r1);
       prefetched = true;
     }
 
     // ---- block updates ----
     if (a.upd1 || a.upd2) {
+      // K-steps in uniform chunks of 4; inside a chunk the four Q fragment
+      // loads are issued first, K-steps past ke read a valid address and
+      // meet zero coefficient fragments, so no lane-divergent branches
       v4d acc1 = {0.0, 0.0, 0.0, 0.0}, acc2 = {0.0, 0.0, 0.0, 0.0};
+      v4d acc1b = {0.0, 0.0, 0.0, 0.0}, acc2b = {0.0, 0.0, 0.0, 0.0};
+      const int kcl = max(kb, min(ke, shared) - 1);
 #pragma unroll
-      for (int i = 0; i < kMaxKF; ++i) {
-        const int k = kb + i;
-        if (k < ke) {
-          const double av = tile[at<TR>(4 * k + lk, mb * 16 + li)];
-          if (a.upd1) acc1 = mfma(av, c1f[i], acc1);
-          if (a.upd2) acc2 = mfma(av, c2f[i], acc2);
+      for (int q = 0; q < kMaxKF / 4; ++q) {
+        if (4 * q >= ke - kb) break;
+        double av[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int k = min(kb + 4 * q + u, kcl);
+          av[u] = tile[at<TR>(4 * k + lk, mb * 16 + li)];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; u += 2) {
+          if (a.upd1) acc1 = mfma(av[u], c1f[4 * q + u], acc1);
+          if (a.upd2) acc2 = mfma(av[u], c2f[4 * q + u], acc2);
+          if (a.upd1) acc1b = mfma(av[u + 1], c1f[4 * q + u + 1], acc1b);
+          if (a.upd2) acc2b = mfma(av[u + 1], c2f[4 * q + u + 1], acc2b);
         }
       }
+      acc1 += acc1b;
+      acc2 += acc2b;
       if (a.upd1) {
 #pragma unroll
         for (int v = 0; v < 4; ++v)
           scr[(kg * TR + mb * 16 + lk + 4 * v) * 17 + li] = acc1[v];
         __syncthreads();
-        combine_solve<TR, KG>(a, tile, scr, a.u1_c0, true, tm1, rd1);
+        combine_solve<NW, TR, KG>(a, tile, scr, a.u1_c0, true, tm1, rd1);
         __syncthreads();
-        store_block<TR>(a, tile, a.u1_c0, a.dst1, a.ldd1, r0, rows);
+        store_block<NW, TR>(a, tile, a.u1_c0, a.dst1, a.ldd1, r0, rows);
         if (mytail >= 0) {
           const double av = tile[at<TR>(4 * mytail + lk, mb * 16 + li)];
           acc2 = mfma(av, c2t, acc2);
@@ -284,25 +325,42 @@ __global__ __launch_bounds__(kT) void pass16_kernel(Args a) {
         for (int v = 0; v < 4; ++v)
           scr[(kg * TR + mb * 16 + lk + 4 * v) * 17 + li] = acc2[v];
         __syncthreads();
-        combine_solve<TR, KG>(a, tile, scr, a.u2_c0, a.trsm2 != 0, tm2, rd2);
+        combine_solve<NW, TR, KG>(a, tile, scr, a.u2_c0, a.trsm2 != 0, tm2,
+                                  rd2);
         __syncthreads();
-        store_block<TR>(a, tile, a.u2_c0, a.dst2, a.ldd2, r0, rows);
+        store_block<NW, TR>(a, tile, a.u2_c0, a.dst2, a.ldd2, r0, rows);
       }
     }
 
-    // ---- Gram accumulation ----
+    // ---- Gram accumulation: two MFMA K-steps per 16-byte LDS load (lane
+    //      group lk takes rows kk + 2 lk and kk + 2 lk + 1) ----
     if (GRAM) {
-#pragma unroll 1
-      for (int kk = 0; kk < TR; kk += 4) {
-        const int r = kk + lk;
 #pragma unroll
-        for (int i = 0; i < MAXT; ++i) {
-          if (tta[i] >= 0) {
-            const double af = tile[at<TR>(tta[i] * 16 + li, r)];
-            const double bf = tile[at<TR>(a.gb0 + ttb[i] * 16 + li, r)];
-            acc[i] = mfma(af, bf, acc[i]);
-          }
+      for (int kk = 0; kk < TR; kk += 8) {
+        const int r = kk + 2 * lk;
+        double2 bf[NTB], af[MAXA];
+#pragma unroll
+        for (int b = 0; b < NTB; ++b)
+          bf[b] = *reinterpret_cast<const double2*>(
+              tile + at<TR>(a.gb0 + b * 16 + li, r));
+#pragma unroll
+        for (int i = 0; i < MAXA; ++i) {
+          // A blocks past the last are computed on a valid block and
+          // never stored
+          const int ta = min(wave + NW * i, nta - 1);
+          af[i] = *reinterpret_cast<const double2*>(
+              tile + at<TR>(ta * 16 + li, r));
         }
+#pragma unroll
+        for (int i = 0; i < MAXA; ++i)
+#pragma unroll
+          for (int b = 0; b < NTB; ++b)
+            acc[i][b] = mfma(af[i].x, bf[b].x, acc[i][b]);
+#pragma unroll
+        for (int i = 0; i < MAXA; ++i)
+#pragma unroll
+          for (int b = 0; b < NTB; ++b)
+            acc[i][b] = mfma(af[i].y, bf[b].y, acc[i][b]);
       }
     }
   }
@@ -311,19 +369,25 @@ __global__ __launch_bounds__(kT) void pass16_kernel(Args a) {
   if (GRAM) {
     double* out = a.partial + (size_t)g * a.ga_p * a.gbn_p;
 #pragma unroll
-    for (int i = 0; i < MAXT; ++i) {
-      if (tta[i] < 0) continue;
+    for (int i = 0; i < MAXA; ++i) {
+      const int ta = wave + NW * i;
+      if (ta >= nta) continue;
 #pragma unroll
-      for (int v = 0; v < 4; ++v)
-        out[(size_t)(ttb[i] * 16 + li) * a.ga_p + tta[i] * 16 + lk + 4 * v] =
-            acc[i][v];
+      for (int b = 0; b < NTB; ++b) {
+        if (ta * 16 >= a.skip_a0 && b * 16 + 16 <= a.skip_b1) continue;
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+          out[(size_t)(b * 16 + li) * a.ga_p + ta * 16 + lk + 4 * v] =
+              acc[i][b][v];
+      }
     }
   }
 }
 
-template <int TR, int MAXT, bool GRAM, int NTB>
-static hipError_t go(const Args& a, int G, size_t lds, hipStream_t st) {
-  auto kern = pass16_kernel<TR, MAXT, GRAM, NTB>;
+template <int NW, int TR, int MAXA, bool GRAM, int NTB>
+static hipError_t go(const Args& a, int G, size_t lds, hipStream_t st,
+                     int* tag) {
+  auto kern = pass16_kernel<NW, TR, MAXA, GRAM, NTB>;
   static bool attr = false;
   if (!attr) {
     (void)hipFuncSetAttribute((const void*)kern,
@@ -331,23 +395,25 @@ static hipError_t go(const Args& a, int G, size_t lds, hipStream_t st) {
                               160 * 1024);
     attr = true;
   }
-  hipLaunchKernelGGL(kern, dim3((unsigned)G), dim3(kT), lds, st, a);
+  // 1NWTTMMG: waves, tile rows, A blocks per wave, B blocks (0: no Gram)
+  *tag = 10000000 + NW * 1000000 + TR * 1000 + MAXA * 10 + (GRAM ? NTB : 0);
+  hipLaunchKernelGGL(kern, dim3((unsigned)G), dim3(NW * 64), lds, st, a);
   return hipGetLastError();
 }
 
 }  // namespace p16
 
-size_t pass16_lds_bytes(int ncols_p, int tr) {
-  const int kg = p16::kW / (tr / 16);
+size_t pass16_lds_bytes(int ncols_p, int tr, int nw) {
+  const int kg = nw / (tr / 16);
   return ((size_t)2 * ncols_p * tr + (size_t)kg * tr * 17 + 512 + 32) *
          sizeof(double);
 }
 
 // Returns hipErrorNotSupported (without launching) when this kernel cannot
-// take the pass; *tag receives the instantiation (1000 + 100*gram + 10*NTB
-// + MAXT/TR code) otherwise.
-hipError_t launch_pass16(const PassArgs<double>& pa, int G, hipStream_t st,
-                         int* tag) {
+// take the pass.  *G_out receives the number of workgroups used (the row
+// split is a function of m and of the chosen shape only).
+hipError_t launch_pass16(const PassArgs<double>& pa, int64_t m, hipStream_t st,
+                         int* tag, int* G_out) {
   using namespace p16;
   const int s = pa.s;
   if (pa.sp != 16 || s % 4 != 0) return hipErrorNotSupported;
@@ -355,19 +421,29 @@ hipError_t launch_pass16(const PassArgs<double>& pa, int G, hipStream_t st,
   const int K1 = pa.upd1 ? pa.u1_c0 : 0;
   const int K2 = pa.upd2 ? pa.u2_c0 : 0;
   const int shared_cols = pa.upd1 ? K1 : K2;
-  int tr = 0;
-  for (int cand : {32, 16}) {
-    const int kg = kW / (cand / 16);
+  // shapes in order of preference: (waves, tile rows, workgroups per CU)
+  const int shapes[3][3] = {{4, 16, 2}, {8, 32, 1}, {8, 16, 1}};
+  int nw = 0, tr = 0, per_cu = 1;
+  for (const auto& sh : shapes) {
+    const int kg = sh[0] / (sh[1] / 16);
     const int per = ((shared_cols / 4) + kg - 1) / kg;
     if (per > kMaxKF) continue;
-    if (pass16_lds_bytes(pa.ncols_p, cand) > 160 * 1024) continue;
-    tr = cand;
+    if (pa.gram && (pa.ga_p / 16 + sh[0] - 1) / sh[0] > 5) continue;
+    if (pass16_lds_bytes(pa.ncols_p, sh[1], sh[0]) * sh[2] > 160 * 1024)
+      continue;
+    nw = sh[0]; tr = sh[1]; per_cu = sh[2];
     break;
   }
-  if (!tr) return hipErrorNotSupported;
+  if (!nw) return hipErrorNotSupported;
+  const int ntb = pa.gbn_p / 16;
+  const int maxa = pa.gram ? (pa.ga_p / 16 + nw - 1) / nw : 0;
+  if (pa.gram && (ntb > 2 || maxa > 5)) return hipErrorNotSupported;
   Args a{};
+  // rows split over 256 * per_cu workgroups (256 CUs on MI355X)
+  const int64_t rpw = round_up64(cdiv(m, 256 * per_cu), 64);
+  const int G = (int)cdiv(m, rpw);
   a.m = pa.m; a.s = s; a.ncols = pa.ncols; a.ncols_p = pa.ncols_p;
-  a.rows_per_wg = pa.rows_per_wg;
+  a.rows_per_wg = rpw;
   a.q = pa.q; a.ldq = pa.ldq; a.nq = pa.nq;
   a.f = pa.f; a.ldf = pa.ldf; a.fcols = pa.fcols;
   a.e = pa.e; a.lde = pa.lde; a.ecols = pa.ecols;
@@ -384,24 +460,22 @@ hipError_t launch_pass16(const PassArgs<double>& pa, int G, hipStream_t st,
   a.gram = pa.gram; a.ga_p = pa.ga_p; a.gb0 = pa.gb0; a.gbn_p = pa.gbn_p;
   a.skip_a0 = pa.skip_a0; a.skip_b1 = pa.skip_b1;
   a.partial = pa.partial;
-  const size_t lds = pass16_lds_bytes(pa.ncols_p, tr);
-  const int ntb = pa.gbn_p / 16;
-  const int ntiles = pa.gram ? (pa.ga_p / 16) * ntb : 0;
-  const int maxt = (ntiles + kW - 1) / kW;
+  *G_out = G;
+  const size_t lds = pass16_lds_bytes(pa.ncols_p, tr, nw);
   if (!pa.gram) {
-    *tag = 1000 + tr;
-    return tr == 32 ? go<32, 1, false, 1>(a, G, lds, st)
-                    : go<16, 1, false, 1>(a, G, lds, st);
+    if (nw == 4) return go<4, 16, 1, false, 1>(a, G, lds, st, tag);
+    if (tr == 32) return go<8, 32, 1, false, 1>(a, G, lds, st, tag);
+    return go<8, 16, 1, false, 1>(a, G, lds, st, tag);
   }
-  if (ntb > 2 || maxt > 9) return hipErrorNotSupported;
-  *tag = 1100 + 10 * ntb + (tr == 32 ? 0 : 5) + (maxt <= 3 ? 0 : maxt <= 5 ? 1 : 2);
-#define P16(TR_, MT_, NTB_)                                               \
-  if (tr == TR_ && ntb == NTB_ && maxt <= MT_)                            \
-    return go<TR_, MT_, true, NTB_>(a, G, lds, st);
-  P16(32, 3, 1) P16(32, 5, 1) P16(32, 9, 1)
-  P16(32, 3, 2) P16(32, 5, 2) P16(32, 9, 2)
-  P16(16, 3, 1) P16(16, 5, 1) P16(16, 9, 1)
-  P16(16, 3, 2) P16(16, 5, 2) P16(16, 9, 2)
+#define P16(NW_, TR_, MA_, NTB_)                                          \
+  if (nw == NW_ && tr == TR_ && ntb == NTB_ && maxa <= MA_)               \
+    return go<NW_, TR_, MA_, true, NTB_>(a, G, lds, st, tag);
+  P16(4, 16, 2, 1) P16(4, 16, 3, 1) P16(4, 16, 5, 1)
+  P16(4, 16, 2, 2) P16(4, 16, 3, 2) P16(4, 16, 5, 2)
+  P16(8, 32, 2, 1) P16(8, 32, 3, 1) P16(8, 32, 5, 1)
+  P16(8, 32, 2, 2) P16(8, 32, 3, 2) P16(8, 32, 5, 2)
+  P16(8, 16, 2, 1) P16(8, 16, 3, 1) P16(8, 16, 5, 1)
+  P16(8, 16, 2, 2) P16(8, 16, 3, 2) P16(8, 16, 5, 2)
 #undef P16
   return hipErrorNotSupported;
 }
