@@ -49,12 +49,12 @@ struct PassArgs {
   const T* q; int64_t ldq; int nq;
   const T* f; int64_t ldf; int fcols;
   const T* e; int64_t lde; int ecols;
-  // update 1: columns [u1_c0, u1_c0 + s) <- (cols - cols[0,u1_c0) C1) T1^-1
+  // update 1: columns [u1_c0, u1_c0 + s) <- cols[0, u1_c0 + s) F1
   int upd1; int u1_c0;
-  const double* c1; const double* t1; T* dst1; int64_t ldd1;
-  // update 2: columns [u2_c0, u2_c0 + s) <- (cols - cols[0,u2_c0) C2) [T2^-1]
-  int upd2; int u2_c0; int trsm2;
-  const double* c2; const double* t2; T* dst2; int64_t ldd2;
+  const double* c1; T* dst1; int64_t ldd1;
+  // update 2: columns [u2_c0, u2_c0 + s) <- cols[0, u2_c0 + s) F2
+  int upd2; int u2_c0;
+  const double* c2; T* dst2; int64_t ldd2;
   // Gram: A = cols [0, ga), B = cols [gb0, gb0 + gbn)
   int gram; int ga_p; int gb0; int gbn_p;
   int a_blocks_per_group;  // 16-column A blocks handled by one y-group
@@ -64,8 +64,12 @@ struct PassArgs {
   double* partial;         // [G][gbn_p][ga_p]
 };
 
-// coefficient matrices are stored row-major with row stride `sp` and zero
-// padding: C (K x s) at C[k * sp + j]; triangular T (s x s) the same.
+// Block updates as one product.  The update B <- (B - Q_{1:j} C) T^{-1} of
+// Alg. 1 / Alg. 2 is evaluated as [Q_{1:j} B] F with the (K + s) x s
+// coefficient matrix F = [-C T^{-1}; T^{-1}] (F = [-C; I] for the updates
+// without a triangular factor), built once per block column by the
+// epilogue.  Coefficient and triangular matrices are stored row-major with
+// row stride `sp` and zero padding: C (K x s) at C[k * sp + j].
 
 // ---------------------------------------------------------------- TSQR ---
 struct TsqrPlan {
@@ -93,7 +97,8 @@ struct Plan {
   int tr_max;             // largest tile the widest pass can afford
   TsqrPlan tsqr;
   // workspace offsets in bytes
-  size_t off_c1, off_c2, off_t1, off_t2, off_gram, off_partial, off_tsqr;
+  size_t off_c1, off_c2, off_t1, off_t2, off_f1, off_f2, off_gram,
+      off_partial, off_tsqr;
   size_t off_scratch_info;
   size_t bytes;
   int64_t gram_ld;        // leading dimension of the reduced Gram matrix
@@ -138,6 +143,13 @@ enum EpiMode : int {
   EPI_R_ASSEMBLE = 4, // BCGSI+: R block column from C2, C1, T2, T1
 };
 
+// coefficient matrices the epilogue leaves for the next streaming pass
+enum CoefMode : int {
+  COEF_NONE = 0,
+  COEF_SCALED = 1,     // F = [-C T^{-1}; T^{-1}]
+  COEF_UNSCALED = 2,   // F = [-C; I]
+};
+
 struct EpiArgs {
   int mode;
   int s, sp;
@@ -146,6 +158,9 @@ struct EpiArgs {
   int chol_s;         // form T2 <- chol(T - S^T S) (P-1S) after eq. (1)
   const double* gram; int64_t gld;
   double* c1; double* c2; double* t1; double* t2;
+  double* f1; double* f2;
+  int f1_mode, f1_rows;   // F1 from (C1, T1), C1 having f1_rows rows
+  int f2_mode, f2_rows;   // F2 from (C2, T2)
   double* r; int64_t ldr;
   bcgs_info* info;
 };

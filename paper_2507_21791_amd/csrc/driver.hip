@@ -67,6 +67,8 @@ bool make_plan(int64_t m, int64_t n, int64_t s, int variant, int precision,
   P.off_t2 = off; off = align256(off + tri);
   P.off_c1 = off; off = align256(off + col);
   P.off_c2 = off; off = align256(off + col);
+  P.off_f1 = off; off = align256(off + col);
+  P.off_f2 = off; off = align256(off + col);
   P.off_gram = off; off = align256(off + P.partial_elems * sizeof(double));
   P.off_partial = off;
   off = align256(off + (size_t)P.G * P.partial_elems * sizeof(double));
@@ -121,13 +123,14 @@ struct Run {
     int nq = 0;                        // Q columns staged
     const T* f = nullptr; int64_t ldf = 0;   // block F (s columns)
     const T* e = nullptr; int64_t lde = 0;   // block E (s columns)
-    bool upd1 = false;                 // Q slot (nq/s - 1): U -> Q
-    bool upd2 = false; bool trsm2 = true;
-    const double* c2 = nullptr; const double* t2 = nullptr;
+    bool upd1 = false;                 // Q slot (nq/s - 1): U -> Q (F1)
+    bool upd2 = false;                 // F block -> dst2 (F2 or c2)
+    const double* c2 = nullptr;        // override of F2
     T* dst2 = nullptr;
     bool gram = false; int gb0 = 0; int gbn = 0;
     bool skip_eu = false;              // skip the E^T U tiles
     int64_t needed = 0;                // Gram entries the method needs
+    bool scaled2 = true;               // update 2 has a triangular factor
   };
 
   void pass(const Pass& d) {
@@ -139,10 +142,10 @@ struct Run {
     a.e = d.e; a.lde = d.lde; a.ecols = d.e ? s : 0;
     a.ncols = a.nq + a.fcols + a.ecols;
     a.upd1 = d.upd1; a.u1_c0 = d.nq - s;
-    a.c1 = dws(p.off_c1); a.t1 = dws(p.off_t1);
+    a.c1 = dws(p.off_f1);
     a.dst1 = Q + (int64_t)(d.nq - s) * ldq; a.ldd1 = ldq;
-    a.upd2 = d.upd2; a.u2_c0 = d.nq; a.trsm2 = d.trsm2;
-    a.c2 = d.c2 ? d.c2 : dws(p.off_c2); a.t2 = d.t2 ? d.t2 : dws(p.off_t2);
+    a.upd2 = d.upd2; a.u2_c0 = d.nq;
+    a.c2 = d.c2 ? d.c2 : dws(p.off_f2);
     a.dst2 = d.dst2; a.ldd2 = ldq;
     a.gram = d.gram;
     a.ga_p = round_up(a.ncols, 16);
@@ -191,7 +194,7 @@ struct Run {
     double flops = 0.0, cols_rw = a.ncols;
     if (d.upd1) { flops += mr * (2.0 * a.u1_c0 * s + (double)s * s); cols_rw += s; }
     if (d.upd2) {
-      flops += mr * (2.0 * a.u2_c0 * s + (d.trsm2 ? (double)s * s : 0.0));
+      flops += mr * (2.0 * a.u2_c0 * s + (d.scaled2 ? (double)s * s : 0.0));
       cols_rw += s;
     }
     if (d.gram) flops += 2.0 * mr * (double)d.needed;
@@ -216,13 +219,19 @@ struct Run {
   }
   int64_t gram_ld_last = 0;
 
-  void epi(int mode, int j, bool has_e, bool chol_s) {
+  // f1/f2: which coefficient matrices the next pass needs (CoefMode) and
+  // the number of rows of C1 / C2 they are built from
+  void epi(int mode, int j, bool has_e, bool chol_s, int f1 = COEF_NONE,
+           int f1_rows = 0, int f2 = COEF_NONE, int f2_rows = 0) {
     EpiArgs e{};
     e.mode = mode; e.s = p.s; e.sp = p.sp; e.j = j;
     e.has_e = has_e; e.chol_s = chol_s;
     e.gram = dws(p.off_gram); e.gld = gram_ld_last;
     e.c1 = dws(p.off_c1); e.c2 = dws(p.off_c2);
     e.t1 = dws(p.off_t1); e.t2 = dws(p.off_t2);
+    e.f1 = dws(p.off_f1); e.f2 = dws(p.off_f2);
+    e.f1_mode = f1; e.f1_rows = f1_rows;
+    e.f2_mode = f2; e.f2_rows = f2_rows;
     e.r = R; e.ldr = ldr; e.info = info;
     check(launch_epilogue(e, st));
   }
@@ -257,7 +266,9 @@ struct Run {
       d.gb0 = s; d.gbn = s;                   // [Q_0 X_1]^T X_1
       d.needed = one ? 2 * s * s : s * s;     // P-2S needs Q_0^T X_1 only
       pass(d);
-      epi(one ? EPI_P1S_INIT : EPI_S_ONLY, 1, false, false);
+      // next: U_1 = (X_1 - Q_0 S_01) S_11^{-1} (P-1S) or V_1 = X_1 - Q_0 S_01
+      epi(one ? EPI_P1S_INIT : EPI_S_ONLY, 1, false, false, COEF_NONE, 0,
+          one ? COEF_SCALED : COEF_UNSCALED, s);
     }
     for (int j = 1; j < q; ++j) {
       const bool has_e = j < q - 1;
@@ -266,18 +277,20 @@ struct Run {
         d.nq = j * s;
         d.upd1 = j >= 2;
         d.f = xb(j); d.ldf = ldx;
-        d.upd2 = true; d.trsm2 = true; d.dst2 = qb(j);
+        d.upd2 = true; d.dst2 = qb(j);
         if (has_e) { d.e = xb(j + 1); d.lde = ldx; }
         d.gram = true; d.gb0 = j * s; d.gbn = has_e ? 2 * s : s;
         d.skip_eu = has_e;
         d.needed = (int64_t)(j + 1) * s * d.gbn + (has_e ? s * s : 0);
         pass(d);
-        epi(EPI_ONE_SYNC, j, has_e, true);
+        // next: Q_j from U_j (Y, Y_jj) and U_{j+1} from X_{j+1} (S, S_jj)
+        epi(EPI_ONE_SYNC, j, has_e, true, COEF_SCALED, j * s,
+            has_e ? COEF_SCALED : COEF_NONE, (j + 1) * s);
       } else {
         Pass u;                       // Q_{j-1} and V_j = X_j - Q S
         u.nq = j * s; u.upd1 = j >= 2;
         u.f = xb(j); u.ldf = ldx;
-        u.upd2 = true; u.trsm2 = false; u.dst2 = qb(j);
+        u.upd2 = true; u.scaled2 = false; u.dst2 = qb(j);
         pass(u);
         tsqr(qb(j), ldq, qb(j), dws(p.off_t2), sp, 1);   // U_j, S_jj
         Pass d;                       // [Q_{0:j-1} U_j]^T [U_j X_{j+1}]
@@ -287,7 +300,9 @@ struct Run {
         d.skip_eu = has_e;
         d.needed = (int64_t)(j + 1) * s * d.gbn;
         pass(d);
-        epi(EPI_ONE_SYNC, j, has_e, false);
+        // next: Q_j from U_j (Y, Y_jj) and V_{j+1} = X_{j+1} - Q S
+        epi(EPI_ONE_SYNC, j, has_e, false, COEF_SCALED, j * s,
+            has_e ? COEF_UNSCALED : COEF_NONE, (j + 1) * s);
       }
     }
     Pass fin;                         // Q_{q-1} = (U - Q Y) Y_kk^{-1}
@@ -303,10 +318,10 @@ struct Run {
       a1.gram = true; a1.gb0 = j * s; a1.gbn = s;
       a1.needed = (int64_t)j * s * s;
       pass(a1);
-      epi(EPI_S_ONLY, j, false, false);
+      epi(EPI_S_ONLY, j, false, false, COEF_NONE, 0, COEF_UNSCALED, j * s);
       Pass a2;                        // V = X_j - Q S
       a2.nq = j * s; a2.f = xb(j); a2.ldf = ldx;
-      a2.upd2 = true; a2.trsm2 = false; a2.dst2 = qb(j);
+      a2.upd2 = true; a2.scaled2 = false; a2.dst2 = qb(j);
       pass(a2);
       tsqr(qb(j), ldq, qb(j), dws(p.off_t2), sp, 1);     // U_j, S_jj
       Pass a3;                        // Y = Q^T U_j
@@ -314,11 +329,11 @@ struct Run {
       a3.gram = true; a3.gb0 = j * s; a3.gbn = s;
       a3.needed = (int64_t)j * s * s;
       pass(a3);
-      epi(EPI_Y_ONLY, j, false, false);
+      epi(EPI_Y_ONLY, j, false, false, COEF_UNSCALED, j * s);
       Pass a4;                        // W = U_j - Q Y
       a4.nq = j * s; a4.f = qb(j); a4.ldf = ldq;
-      a4.upd2 = true; a4.trsm2 = false; a4.dst2 = qb(j);
-      a4.c2 = dws(p.off_c1);
+      a4.upd2 = true; a4.scaled2 = false; a4.dst2 = qb(j);
+      a4.c2 = dws(p.off_f1);
       pass(a4);
       tsqr(qb(j), ldq, qb(j), dws(p.off_t1), sp, 1);     // Q_j, Y_jj
       epi(EPI_R_ASSEMBLE, j, false, false);

@@ -102,8 +102,68 @@ __device__ void assemble_r(const EpiArgs& a, const double* c1,
   }
 }
 
+// F = [-C T^{-1}; T^{-1}] (scaled) or [-C; I] (unscaled), C with K rows.
+// T^{-1} by back substitution, one column per thread, in FP64.
+__device__ void make_coef(EpiSmem& sm, double* F, const double* C, int K,
+                          const double* T, int scaled, int s, int sp) {
+  const int tid = threadIdx.x;
+  double* Ti = sm.B;                  // s x s row-major
+  if (scaled) {
+    if (tid < s) {
+      const int j = tid;
+      for (int i = s - 1; i >= 0; --i) {
+        double x = 0.0;
+        if (i <= j) {
+          x = (i == j) ? 1.0 : 0.0;
+          for (int k = i + 1; k <= j; ++k) x -= T[i * sp + k] * Ti[k * s + j];
+          x /= T[i * sp + i];
+        }
+        Ti[i * s + j] = x;
+      }
+    }
+  } else {
+    for (int e = tid; e < s * s; e += kThreads)
+      Ti[e] = (e / s == e % s) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  for (int e = tid; e < K * sp; e += kThreads) {
+    const int i = e / sp, c = e % sp;
+    double v = 0.0;
+    if (c < s) {
+      if (scaled) {
+        for (int k = 0; k <= c; ++k) v -= C[i * sp + k] * Ti[k * s + c];
+      } else {
+        v = -C[i * sp + c];
+      }
+    }
+    F[e] = v;
+  }
+  for (int e = tid; e < s * sp; e += kThreads) {
+    const int i = e / sp, c = e % sp;
+    F[(size_t)(K + i) * sp + c] = c < s ? Ti[i * s + c] : 0.0;
+  }
+  __syncthreads();
+}
+
+__device__ void make_coefs(EpiSmem& sm, const EpiArgs& a) {
+  __syncthreads();
+  if (a.f1_mode != COEF_NONE)
+    make_coef(sm, a.f1, a.c1, a.f1_rows, a.t1, a.f1_mode == COEF_SCALED,
+              a.s, a.sp);
+  if (a.f2_mode != COEF_NONE)
+    make_coef(sm, a.f2, a.c2, a.f2_rows, a.t2, a.f2_mode == COEF_SCALED,
+              a.s, a.sp);
+}
+
+__device__ void epilogue_body(EpiArgs a, EpiSmem& sm);
+
 __global__ __launch_bounds__(kThreads) void epilogue_kernel(EpiArgs a) {
   __shared__ EpiSmem sm;
+  epilogue_body(a, sm);
+  make_coefs(sm, a);
+}
+
+__device__ void epilogue_body(EpiArgs a, EpiSmem& sm) {
   const int tid = threadIdx.x;
   const int s = a.s, sp = a.sp, js = a.j * s;
 

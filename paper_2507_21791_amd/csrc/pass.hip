@@ -42,19 +42,18 @@ __device__ __forceinline__ const T* col_src(const PassArgs<T>& a, int c,
 }
 
 // Block update of the tile columns [uc0, uc0 + s):
-//   W = tile[:, uc0:uc0+s] - tile[:, 0:uc0] * C        (MFMA, K = uc0)
-//   Y = W * T^{-1}  (if trsm; row-wise substitution)    -> tile and HBM.
+//   out = tile[:, 0:uc0+s] * F        (MFMA over K = uc0 + s columns)
+// with F = [-C T^{-1}; T^{-1}] or [-C; I] (see common.h); the K range is
+// split over the waves and the partial products are summed in LDS.
 template <typename T>
 __device__ void block_update(const PassArgs<T>& a, double* tile, int trp,
-                             double* scr, int uc0, const double* __restrict__ C,
-                             const double* __restrict__ Tm,
-                             const double* rdiag, bool trsm, T* dst,
-                             int64_t ldd, int64_t r0, int rows) {
+                             double* scr, int uc0, const double* __restrict__ F,
+                             T* dst, int64_t ldd, int64_t r0, int rows) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int tr = a.tr, sp = a.sp, s = a.s;
   const int mb = tr >> 4, nb = sp >> 4, nt = mb * nb;
   const int ksplit = nt >= kWaves ? 1 : kWaves / nt;
-  const int K = uc0;
+  const int K = uc0 + s;
   const int ksteps = (K + 3) >> 2;
   const int kper = (ksteps + ksplit - 1) / ksplit;
   const int srow = sp + 1;     // padded scratch row
@@ -69,7 +68,7 @@ __device__ void block_update(const PassArgs<T>& a, double* tile, int trp,
       double av = 0.0, bv = 0.0;
       if (k < K) {
         av = tile[k * trp + rb * 16 + li];
-        bv = C[k * sp + cb * 16 + li];
+        bv = F[k * sp + cb * 16 + li];
       }
       acc = mfma_f64(av, bv, acc);
     }
@@ -79,27 +78,13 @@ __device__ void block_update(const PassArgs<T>& a, double* tile, int trp,
       out[(rb * 16 + lk + 4 * v) * srow + cb * 16 + li] = acc[v];
   }
   __syncthreads();
-  if (tid < tr) {
-    const int r = tid;
-    double* w = scr + r * srow;  // this row's workspace (slice ks = 0)
-    for (int c = 0; c < s; ++c) {
-      double sum = 0.0;
-      for (int ks = 0; ks < ksplit; ++ks)
-        sum += scr[(size_t)ks * tr * srow + r * srow + c];
-      w[c] = tile[(uc0 + c) * trp + r] - sum;
-    }
-    if (trsm) {
-      // W T^{-1}: y_j = (w_j - sum_{i<j} y_i T_ij) / T_jj, column-oriented
-      for (int j = 0; j < s; ++j) {
-        const double yj = w[j] * rdiag[j];
-        w[j] = yj;
-        for (int l = j + 1; l < s; ++l) w[l] -= yj * Tm[j * sp + l];
-      }
-    }
-    for (int c = 0; c < s; ++c) tile[(uc0 + c) * trp + r] = w[c];
-    if (r < rows)
-      for (int c = 0; c < s; ++c)
-        dst[(int64_t)c * ldd + r0 + r] = static_cast<T>(w[c]);
+  for (int e = tid; e < tr * s; e += kThreads) {
+    const int r = e % tr, c = e / tr;
+    double sum = 0.0;
+    for (int ks = 0; ks < ksplit; ++ks)
+      sum += scr[(size_t)ks * tr * srow + r * srow + c];
+    tile[(uc0 + c) * trp + r] = sum;
+    if (r < rows) dst[(int64_t)c * ldd + r0 + r] = static_cast<T>(sum);
   }
   __syncthreads();
 }
@@ -109,8 +94,7 @@ __global__ __launch_bounds__(kThreads) void pass_kernel(PassArgs<T> a) {
   extern __shared__ double lds[];
   const int tr = a.tr, trp = tr + 1;
   double* tile = lds;
-  double* rdiag = tile + (size_t)a.ncols_p * trp;   // 2 * 64
-  double* scr = rdiag + 2 * kMaxS;
+  double* scr = tile + (size_t)a.ncols_p * trp;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int li = lane & 15, lk = lane >> 4;
   const int h = blockIdx.x % a.groups;
@@ -118,10 +102,6 @@ __global__ __launch_bounds__(kThreads) void pass_kernel(PassArgs<T> a) {
   const int64_t row_begin = g * a.rows_per_wg;
   const int64_t row_end = min(a.m, row_begin + a.rows_per_wg);
 
-  if (tid < a.s) {
-    if (a.upd1) rdiag[tid] = 1.0 / a.t1[tid * a.sp + tid];
-    if (a.upd2 && a.trsm2) rdiag[kMaxS + tid] = 1.0 / a.t2[tid * a.sp + tid];
-  }
 
   v4d acc[MAXA][NTB];
   int ta_of[MAXA];
@@ -154,11 +134,11 @@ __global__ __launch_bounds__(kThreads) void pass_kernel(PassArgs<T> a) {
     __syncthreads();
     // 2-3. block updates
     if (a.upd1)
-      block_update(a, tile, trp, scr, a.u1_c0, a.c1, a.t1, rdiag, true,
-                   a.dst1, a.ldd1, r0, rows);
+      block_update(a, tile, trp, scr, a.u1_c0, a.c1, a.dst1, a.ldd1, r0,
+                   rows);
     if (a.upd2)
-      block_update(a, tile, trp, scr, a.u2_c0, a.c2, a.t2, rdiag + kMaxS,
-                   a.trsm2 != 0, a.dst2, a.ldd2, r0, rows);
+      block_update(a, tile, trp, scr, a.u2_c0, a.c2, a.dst2, a.ldd2, r0,
+                   rows);
     // 4. Gram accumulation over this tile's rows
     if (GRAM) {
       for (int kk = 0; kk < tr; kk += 4) {
@@ -238,7 +218,7 @@ template <typename T>
 size_t pass_lds_bytes(const PassArgs<T>& a) {
   const int nt = (a.tr / 16) * (a.sp / 16);
   const int ksplit = nt >= kWaves ? 1 : kWaves / nt;
-  size_t d = (size_t)a.ncols_p * (a.tr + 1) + 2 * kMaxS +
+  size_t d = (size_t)a.ncols_p * (a.tr + 1) +
              (size_t)ksplit * a.tr * (a.sp + 1);
   return d * sizeof(double);
 }

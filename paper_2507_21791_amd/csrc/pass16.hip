@@ -15,12 +15,11 @@
 //    per-column key, which keeps both MFMA fragment patterns (16 columns x
 //    4 rows for the Gram, 4 columns x 16 rows for the updates) free of bank
 //    conflicts.
-//  * Block updates W = B - Q C: waves = (TR/16 row blocks) x (KG K-ranges);
-//    every wave keeps its slice of C's MFMA fragments in registers for the
-//    whole kernel; both updates of a pass share the Q fragments; partial
-//    sums meet in LDS, then 16 lanes per row run the substitution with the
-//    upper-triangular factor (lane j owns column j; the pivot value is
-//    broadcast along the row with a DPP row_newbcast move).
+//  * Block updates B <- [Q B] F (F = [-C T^{-1}; T^{-1}], see common.h):
+//    waves = (TR/16 row blocks) x (KG K-ranges); every wave keeps its slice
+//    of the coefficient fragments in registers for the whole kernel; both
+//    updates of a pass share the Q fragments; the K-range partial products
+//    are summed in LDS.
 //  * Gram A^T B: the 16x16 output tiles are dealt round-robin to the waves,
 //    which accumulate them in registers over the whole row range.
 #include "common.h"
@@ -39,7 +38,7 @@ __device__ __forceinline__ v4d mfma(double a, double b, v4d c) {
 // swizzle key of column c: a permutation of the granule index
 template <int TR>
 __device__ __forceinline__ int swz(int c) {
-  if (TR == 32) return ((c & 1) << 3) | ((c >> 1) & 7);
+  if (TR >= 32) return ((c & 1) << 3) | ((c >> 1) & 7);
   return (c >> 1) & 7;
 }
 
@@ -57,9 +56,8 @@ struct Args {
   const double* f; int64_t ldf; int fcols;
   const double* e; int64_t lde; int ecols;
   int dma;                       // all leading dimensions even: 16B loads
-  int upd1, u1_c0; const double* c1; const double* t1; double* dst1; int64_t ldd1;
-  int upd2, u2_c0, trsm2; const double* c2; const double* t2; double* dst2;
-  int64_t ldd2;
+  int upd1, u1_c0; const double* c1; double* dst1; int64_t ldd1;
+  int upd2, u2_c0; const double* c2; double* dst2; int64_t ldd2;
   int gram, ga_p, gb0, gbn_p, skip_a0, skip_b1;
   double* partial;
 };
@@ -110,62 +108,22 @@ __device__ void tile_sync(const Args& a, double* buf, int64_t r0, int rows) {
   }
 }
 
-// Value of v held by lane J of this lane's row of 16 (DPP row_newbcast).
-template <int J>
-__device__ __forceinline__ double row_bcast(double v) {
-  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x150 + J,
-                                             0xf, 0xf, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x150 + J,
-                                             0xf, 0xf, false);
-  return __hiloint2double(hi, lo);
-}
-
-// Combine the K-range partial sums of one block update, subtract them from
-// the block, apply T^{-1} by substitution (16 lanes per row, lane c owns
-// column c) and store the result in the tile.  scr: [KG][TR][17] doubles.
-// tmt: the factor transposed and masked, tmt[c * 16 + j] = T(j, c) for
-// j < c and 0 otherwise; rdiag[j] = 1 / T(j, j) (0 for j >= s).  Step j:
-// y_j = w_j / T_jj (broadcast from lane j), w_c -= y_j T(j, c) for c > j,
-// and lane j keeps y_j.  Branch-free; the factor is read four steps ahead.
+// Sum the K-range partial products of one block update into the tile
+// columns [uc0, uc0 + s).  scr: [KG][TR][17] doubles.
 template <int NW, int TR, int KG>
-__device__ __forceinline__ void combine_solve(const Args& a, double* tile,
-                                              const double* scr, int uc0,
-                                              bool trsm, const double* tmt,
-                                              const double* rdiag) {
+__device__ __forceinline__ void combine(const Args& a, double* tile,
+                                        const double* scr, int uc0) {
   const int s = a.s;
   for (int t = threadIdx.x; t < TR * 16; t += NW * 64) {
     const int r = t >> 4, c = t & 15;
+    if (c >= s) continue;
     double part[KG];
 #pragma unroll
     for (int k = 0; k < KG; ++k) part[k] = scr[(k * TR + r) * 17 + c];
-    const double x = c < s ? tile[at<TR>(uc0 + c, r)] : 0.0;
     double sum = 0.0;
 #pragma unroll
     for (int k = 0; k < KG; ++k) sum += part[k];
-    double w = c < s ? x - sum : 0.0;
-    if (trsm) {
-      const double2* tv = reinterpret_cast<const double2*>(tmt + c * 16);
-      const double2* rv = reinterpret_cast<const double2*>(rdiag);
-#define BCGS_STEP(J, TJ, RJ)                                            \
-  {                                                                     \
-    const double yj = row_bcast<J>(w) * (RJ);                           \
-    w = fma(-yj, (TJ), w);                                              \
-    w = (c == J) ? yj : w;                                              \
-  }
-#define BCGS_QUAD(Q)                                                    \
-  {                                                                     \
-    const double2 t0 = tv[2 * Q], t1 = tv[2 * Q + 1];                   \
-    const double2 r0 = rv[2 * Q], r1 = rv[2 * Q + 1];                   \
-    BCGS_STEP(4 * Q + 0, t0.x, r0.x)                                    \
-    BCGS_STEP(4 * Q + 1, t0.y, r0.y)                                    \
-    BCGS_STEP(4 * Q + 2, t1.x, r1.x)                                    \
-    BCGS_STEP(4 * Q + 3, t1.y, r1.y)                                    \
-  }
-      BCGS_QUAD(0) BCGS_QUAD(1) BCGS_QUAD(2) BCGS_QUAD(3)
-#undef BCGS_QUAD
-#undef BCGS_STEP
-    }
-    if (c < s) tile[at<TR>(uc0 + c, r)] = w;
+    tile[at<TR>(uc0 + c, r)] = sum;
   }
 }
 
@@ -192,10 +150,6 @@ void pass16_kernel(Args a) {
   double* buf0 = lds;
   double* buf1 = lds + tile_elems;
   double* scr = buf1 + tile_elems;                  // KG * TR * 17
-  double* tm1 = scr + KG * TR * 17;                 // 16 x 16
-  double* tm2 = tm1 + 256;
-  double* rd1 = tm2 + 256;                          // 16
-  double* rd2 = rd1 + 16;
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int li = lane & 15, lk = lane >> 4;
@@ -204,11 +158,16 @@ void pass16_kernel(Args a) {
   const int64_t row_begin = g * a.rows_per_wg;
   const int64_t row_end = min(a.m, row_begin + a.rows_per_wg);
 
-  // ---- prologue: coefficients, triangular factors, zero padding --------
+  // ---- prologue: coefficient fragments --------------------------------
+  // K-steps (4 columns each) of update 1: [0, nks1) over Q_{1:k-1} (shared
+  // with update 2) and [nks1, nks1 + sq) over its own block; of update 2:
+  // [0, nks1) shared, [nks1, nks2) over the block update 1 rewrites (after
+  // it), and [nks2, nks2 + sq) over its own block F.  Without update 1,
+  // update 2's steps [0, nks2) are all "shared".
   const int s = a.s;
-  const int nks1 = a.upd1 ? a.u1_c0 / 4 : 0;       // shared K-steps
+  const int sq = s / 4;
+  const int nks1 = a.upd1 ? a.u1_c0 / 4 : 0;
   const int nks2 = a.upd2 ? a.u2_c0 / 4 : 0;
-  // update 2's K-steps [0, shared) run together with update 1's
   const int shared = a.upd1 ? nks1 : nks2;
   const int per = (shared + KG - 1) / KG;
   const int kb = kg * per, ke = min(shared, kb + per);
@@ -224,22 +183,16 @@ void pass16_kernel(Args a) {
       if (a.upd2) c2f[i] = a.c2[row * 16 + li];
     }
   }
-  // update 2's remaining K-steps (over the block update 1 produced)
-  const int tail0 = a.upd1 ? nks1 : nks2;
-  const int ntail = a.upd2 ? nks2 - tail0 : 0;      // <= 4
-  double c2t = 0.0;
-  const int mytail = kg < ntail ? tail0 + kg : -1;   // one per K range
-  if (mytail >= 0) c2t = a.c2[(4 * mytail + lk) * 16 + li];
-  if (tid < 256) {
-    // transposed, strictly-upper-masked factors: tm[c * 16 + j] = T(j, c)
-    const int c = tid >> 4, j = tid & 15;
-    const bool up = j < c;
-    tm1[tid] = (a.upd1 && up) ? a.t1[j * 16 + c] : 0.0;
-    tm2[tid] = (a.upd2 && a.trsm2 && up) ? a.t2[j * 16 + c] : 0.0;
-  }
-  if (tid < 16) {
-    rd1[tid] = (a.upd1 && tid < s) ? 1.0 / a.t1[tid * 17] : 0.0;
-    rd2[tid] = (a.upd2 && a.trsm2 && tid < s) ? 1.0 / a.t2[tid * 17] : 0.0;
+  // per-block steps, step t < sq goes to K range t % KG
+  constexpr int kTail = (4 + KG - 1) / KG;
+  const int ntail = (a.upd1 && a.upd2) ? sq : 0;   // update 2 over new block
+  double c1o[kTail], c2o[kTail], c2t[kTail];
+#pragma unroll
+  for (int u = 0; u < kTail; ++u) {
+    const int t = kg + KG * u;
+    c1o[u] = (a.upd1 && t < sq) ? a.c1[(4 * (nks1 + t) + lk) * 16 + li] : 0.0;
+    c2o[u] = (a.upd2 && t < sq) ? a.c2[(4 * (nks2 + t) + lk) * 16 + li] : 0.0;
+    c2t[u] = t < ntail ? a.c2[(4 * (nks1 + t) + lk) * 16 + li] : 0.0;
   }
   for (int idx = a.ncols * TR + tid; idx < tile_elems; idx += kT) {
     buf0[idx] = 0.0;
@@ -302,6 +255,19 @@ void pass16_kernel(Args a) {
           if (a.upd2) acc2b = mfma(av[u + 1], c2f[4 * q + u + 1], acc2b);
         }
       }
+      // own-block steps (independent of update 1's result)
+#pragma unroll
+      for (int u = 0; u < kTail; ++u) {
+        const int t = kg + KG * u;
+        if (t < sq) {
+          if (a.upd1)
+            acc1b = mfma(tile[at<TR>(4 * (nks1 + t) + lk, mb * 16 + li)],
+                         c1o[u], acc1b);
+          if (a.upd2)
+            acc2b = mfma(tile[at<TR>(4 * (nks2 + t) + lk, mb * 16 + li)],
+                         c2o[u], acc2b);
+        }
+      }
       acc1 += acc1b;
       acc2 += acc2b;
       if (a.upd1) {
@@ -309,24 +275,24 @@ void pass16_kernel(Args a) {
         for (int v = 0; v < 4; ++v)
           scr[(kg * TR + mb * 16 + lk + 4 * v) * 17 + li] = acc1[v];
         __syncthreads();
-        combine_solve<NW, TR, KG>(a, tile, scr, a.u1_c0, true, tm1, rd1);
+        combine<NW, TR, KG>(a, tile, scr, a.u1_c0);
         __syncthreads();
         store_block<NW, TR>(a, tile, a.u1_c0, a.dst1, a.ldd1, r0, rows);
-        if (mytail >= 0) {
-          const double av = tile[at<TR>(4 * mytail + lk, mb * 16 + li)];
-          acc2 = mfma(av, c2t, acc2);
+        // update 2 over the block update 1 just formed
+#pragma unroll
+        for (int u = 0; u < kTail; ++u) {
+          const int t = kg + KG * u;
+          if (t < ntail)
+            acc2 = mfma(tile[at<TR>(4 * (nks1 + t) + lk, mb * 16 + li)],
+                        c2t[u], acc2);
         }
-      } else if (mytail >= 0) {
-        const double av = tile[at<TR>(4 * mytail + lk, mb * 16 + li)];
-        acc2 = mfma(av, c2t, acc2);
       }
       if (a.upd2) {
 #pragma unroll
         for (int v = 0; v < 4; ++v)
           scr[(kg * TR + mb * 16 + lk + 4 * v) * 17 + li] = acc2[v];
         __syncthreads();
-        combine_solve<NW, TR, KG>(a, tile, scr, a.u2_c0, a.trsm2 != 0, tm2,
-                                  rd2);
+        combine<NW, TR, KG>(a, tile, scr, a.u2_c0);
         __syncthreads();
         store_block<NW, TR>(a, tile, a.u2_c0, a.dst2, a.ldd2, r0, rows);
       }
@@ -405,8 +371,7 @@ static hipError_t go(const Args& a, int G, size_t lds, hipStream_t st,
 
 size_t pass16_lds_bytes(int ncols_p, int tr, int nw) {
   const int kg = nw / (tr / 16);
-  return ((size_t)2 * ncols_p * tr + (size_t)kg * tr * 17 + 512 + 32) *
-         sizeof(double);
+  return ((size_t)2 * ncols_p * tr + (size_t)kg * tr * 17) * sizeof(double);
 }
 
 // Returns hipErrorNotSupported (without launching) when this kernel cannot
@@ -422,7 +387,8 @@ hipError_t launch_pass16(const PassArgs<double>& pa, int64_t m, hipStream_t st,
   const int K2 = pa.upd2 ? pa.u2_c0 : 0;
   const int shared_cols = pa.upd1 ? K1 : K2;
   // shapes in order of preference: (waves, tile rows, workgroups per CU)
-  const int shapes[3][3] = {{4, 16, 2}, {8, 32, 1}, {8, 16, 1}};
+  const int shapes[5][3] = {{4, 64, 2}, {4, 32, 2}, {4, 16, 2},
+                            {8, 32, 1}, {8, 16, 1}};
   int nw = 0, tr = 0, per_cu = 1;
   for (const auto& sh : shapes) {
     const int kg = sh[0] / (sh[1] / 16);
@@ -453,16 +419,18 @@ hipError_t launch_pass16(const PassArgs<double>& pa, int64_t m, hipStream_t st,
   a.dma = (pa.ldq % 2 == 0) && al16(pa.q) &&
           (!pa.fcols || (pa.ldf % 2 == 0 && al16(pa.f))) &&
           (!pa.ecols || (pa.lde % 2 == 0 && al16(pa.e)));
-  a.upd1 = pa.upd1; a.u1_c0 = pa.u1_c0; a.c1 = pa.c1; a.t1 = pa.t1;
+  a.upd1 = pa.upd1; a.u1_c0 = pa.u1_c0; a.c1 = pa.c1;
   a.dst1 = pa.dst1; a.ldd1 = pa.ldd1;
-  a.upd2 = pa.upd2; a.u2_c0 = pa.u2_c0; a.trsm2 = pa.trsm2;
-  a.c2 = pa.c2; a.t2 = pa.t2; a.dst2 = pa.dst2; a.ldd2 = pa.ldd2;
+  a.upd2 = pa.upd2; a.u2_c0 = pa.u2_c0;
+  a.c2 = pa.c2; a.dst2 = pa.dst2; a.ldd2 = pa.ldd2;
   a.gram = pa.gram; a.ga_p = pa.ga_p; a.gb0 = pa.gb0; a.gbn_p = pa.gbn_p;
   a.skip_a0 = pa.skip_a0; a.skip_b1 = pa.skip_b1;
   a.partial = pa.partial;
   *G_out = G;
   const size_t lds = pass16_lds_bytes(pa.ncols_p, tr, nw);
   if (!pa.gram) {
+    if (nw == 4 && tr == 64) return go<4, 64, 1, false, 1>(a, G, lds, st, tag);
+    if (nw == 4 && tr == 32) return go<4, 32, 1, false, 1>(a, G, lds, st, tag);
     if (nw == 4) return go<4, 16, 1, false, 1>(a, G, lds, st, tag);
     if (tr == 32) return go<8, 32, 1, false, 1>(a, G, lds, st, tag);
     return go<8, 16, 1, false, 1>(a, G, lds, st, tag);
@@ -470,6 +438,10 @@ hipError_t launch_pass16(const PassArgs<double>& pa, int64_t m, hipStream_t st,
 #define P16(NW_, TR_, MA_, NTB_)                                          \
   if (nw == NW_ && tr == TR_ && ntb == NTB_ && maxa <= MA_)               \
     return go<NW_, TR_, MA_, true, NTB_>(a, G, lds, st, tag);
+  P16(4, 64, 2, 1) P16(4, 64, 3, 1) P16(4, 64, 5, 1)
+  P16(4, 64, 2, 2) P16(4, 64, 3, 2) P16(4, 64, 5, 2)
+  P16(4, 32, 2, 1) P16(4, 32, 3, 1) P16(4, 32, 5, 1)
+  P16(4, 32, 2, 2) P16(4, 32, 3, 2) P16(4, 32, 5, 2)
   P16(4, 16, 2, 1) P16(4, 16, 3, 1) P16(4, 16, 5, 1)
   P16(4, 16, 2, 2) P16(4, 16, 3, 2) P16(4, 16, 5, 2)
   P16(8, 32, 2, 1) P16(8, 32, 3, 1) P16(8, 32, 5, 1)
