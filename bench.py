@@ -119,24 +119,51 @@ def kernel_name(kind, tag):
             "other": "fill_kernel"}.get(kind, kind)
 
 
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE summary, or None when the summary is missing or
+    was taken from different kernel sources."""
+    root = os.path.dirname(os.path.abspath(__file__))
+    path = os.path.join(root, "profiles", "p1s_tall_hbm_traffic.txt")
+    try:
+        from paper_2507_21791_amd.prof_summary import source_digest
+        lines = open(path).read().splitlines()
+    except OSError:
+        return None
+    digest = [l.split(":")[1].strip() for l in lines
+              if l.startswith("# kernel sources digest:")]
+    if not digest or digest[0] != source_digest(root):
+        return None
+    want = kernel.replace(" ", "")
+    for l in lines:
+        if l.startswith("#") or l.startswith("  "):
+            continue
+        parts = l.rsplit(None, 4)
+        if len(parts) == 5 and parts[0].replace(" ", "") == want:
+            return float(parts[4]) * 1e9
+    return None
+
+
 def roofline(dom):
     t_hbm = dom["bytes"] / (HBM_PEAK_GBS * 1e9)
     t_fp = dom["flops"] / (FP64_PEAK_TFS * 1e12)
     per_launch_ms = dom["ms"] / dom["n"]
+    traffic = measured_traffic(kernel_name(dom["kind"], dom["tag"]))
     if t_fp >= t_hbm:
         achieved = dom["flops"] / dom["n"] / (per_launch_ms * 1e-3) / 1e12
         return {"bound": "mfma", "achieved": round(achieved, 3),
                 "peak": FP64_PEAK_TFS, "unit": "TFLOP/s",
-                "frac": round(achieved / FP64_PEAK_TFS, 4), "traffic": None,
+                "frac": round(achieved / FP64_PEAK_TFS, 4), "traffic": traffic,
                 "kernel": kernel_name(dom["kind"], dom["tag"]),
                 "launches_per_step": dom["n"],
                 "avg_launch_ms": round(per_launch_ms, 4),
+                "algorithmic_bytes": dom["bytes"] / dom["n"],
                 "hbm_gbs": round(dom["bytes"] / dom["n"] /
                                  (per_launch_ms * 1e-3) / 1e9, 1)}
     achieved = dom["bytes"] / dom["n"] / (per_launch_ms * 1e-3) / 1e9
     return {"bound": "hbm", "achieved": round(achieved, 1),
             "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
             "kernel": kernel_name(dom["kind"], dom["tag"]),
             "launches_per_step": dom["n"],
             "avg_launch_ms": round(per_launch_ms, 4)}

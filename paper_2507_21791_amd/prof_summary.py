@@ -1,0 +1,148 @@
+"""Condense rocprofv3 CSV output into the short text summaries kept under
+profiles/.
+
+    python -m paper_2507_21791_amd.prof_summary trace  <dir> <prefix> "<cmd>"
+    python -m paper_2507_21791_amd.prof_summary counters <fetch_dir>
+           <write_dir> <prefix> "<cmd>"
+
+`trace` reads <dir>/<prefix>_kernel_trace.csv (a --kernel-trace run) and
+prints per-kernel launch counts and durations for this library's kernels
+(the input generation by torch/rocBLAS/rocSOLVER is summed on one line).
+
+`counters` reads the FETCH_SIZE and WRITE_SIZE runs (one counter per run)
+and prints the per-launch HBM traffic of every library kernel, scaled by
+what the same counters read for the plain 1 GiB device copies that
+`bench.py --copy-calibration` performs (copyBuffer dispatches with 131072
+work-items).  The scale factors make the counters comparable to bytes.
+"""
+
+import csv
+import hashlib
+import os
+import re
+import sys
+from collections import OrderedDict, defaultdict
+
+GIB_KIB = 1 << 20
+
+
+def short_name(name):
+    n = re.sub(r"\(.*", "", name)
+    n = n.replace("void ", "").replace("bcgs::", "")
+    n = n.replace("p16::", "").replace("tq::", "tsqr_")
+    return n.strip()
+
+
+def ours(name):
+    return "bcgs::" in name
+
+
+def source_digest(root):
+    """sha256 over the kernel sources, to tell whether counters are stale."""
+    h = hashlib.sha256()
+    cdir = os.path.join(root, "paper_2507_21791_amd", "csrc")
+    for f in sorted(os.listdir(cdir)):
+        if f.endswith((".hip", ".h")):
+            with open(os.path.join(cdir, f), "rb") as fh:
+                h.update(f.encode())
+                h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def trace(d, prefix, cmd):
+    rows = list(csv.DictReader(open(os.path.join(
+        d, f"{prefix}_kernel_trace.csv"))))
+    agg = OrderedDict()
+    other_ns, other_n = 0, 0
+    for r in rows:
+        dt = int(r["End_Timestamp"]) - int(r["Start_Timestamp"])
+        if not ours(r["Kernel_Name"]):
+            other_ns += dt
+            other_n += 1
+            continue
+        k = short_name(r["Kernel_Name"])
+        a = agg.setdefault(k, [0, 0, None, 0])
+        a[0] += 1
+        a[1] += dt
+        a[2] = dt if a[2] is None else min(a[2], dt)
+        a[3] = max(a[3], dt)
+    out = [f"# rocprofv3 kernel trace summary", f"# command: {cmd}",
+           "# library kernels, sorted by total time (all launches in the run)",
+           f"{'kernel':52s} {'calls':>6s} {'total_ms':>10s} {'avg_us':>10s}"
+           f" {'min_us':>9s} {'max_us':>9s}"]
+    for k, (n, tot, lo, hi) in sorted(agg.items(), key=lambda kv: -kv[1][1]):
+        out.append(f"{k:52s} {n:6d} {tot / 1e6:10.3f} {tot / n / 1e3:10.1f}"
+                   f" {lo / 1e3:9.1f} {hi / 1e3:9.1f}")
+    out.append(f"{'(input generation and copies: torch/rocBLAS/rocSOLVER)':52s}"
+               f" {other_n:6d} {other_ns / 1e6:10.3f}")
+    return "\n".join(out)
+
+
+def _counter(d, name):
+    f = [x for x in os.listdir(d) if x.endswith("counter_collection.csv")][0]
+    res = []
+    for r in csv.DictReader(open(os.path.join(d, f))):
+        if r["Counter_Name"] == name:
+            res.append((r["Kernel_Name"], int(r["Grid_Size"]),
+                        float(r["Counter_Value"])))
+    return res
+
+
+def counters(dfetch, dwrite, prefix, cmd, root):
+    fe = _counter(dfetch, "FETCH_SIZE")
+    wr = _counter(dwrite, "WRITE_SIZE")
+    cal = {}
+    for tag, rows in (("FETCH_SIZE", fe), ("WRITE_SIZE", wr)):
+        vals = [v for n, g, v in rows if "copyBuffer" in n and g == 131072]
+        vals = [v for v in vals if v > 0.25 * GIB_KIB]
+        vals = vals[-3:]
+        cal[tag] = GIB_KIB / (sum(vals) / len(vals)) if vals else float("nan")
+    per = defaultdict(lambda: [0, 0.0, 0.0])
+    seq = []
+    for (n, g, f), (n2, g2, w) in zip(
+            [x for x in fe if ours(x[0])], [x for x in wr if ours(x[0])]):
+        k = short_name(n)
+        a = per[k]
+        a[0] += 1
+        fb = f * 1024 * cal["FETCH_SIZE"]
+        wb = w * 1024 * cal["WRITE_SIZE"]
+        a[1] += fb
+        a[2] += wb
+        seq.append((k, fb, wb))
+    out = ["# rocprofv3 HBM traffic summary (FETCH_SIZE run, then WRITE_SIZE "
+           "run)", f"# command (twice, --pmc FETCH_SIZE / --pmc WRITE_SIZE): "
+           f"{cmd}",
+           f"# kernel sources digest: {source_digest(root)}",
+           "# calibration: 1 GiB plain device copy reads "
+           f"{GIB_KIB / cal['FETCH_SIZE']:.0f} KiB FETCH_SIZE and "
+           f"{GIB_KIB / cal['WRITE_SIZE']:.0f} KiB WRITE_SIZE;",
+           f"# scale factors FETCH x{cal['FETCH_SIZE']:.4f}, "
+           f"WRITE x{cal['WRITE_SIZE']:.4f}",
+           "# per-launch averages in GB (1e9 bytes) after scaling",
+           f"{'kernel':52s} {'calls':>6s} {'read_GB':>9s} {'write_GB':>9s}"
+           f" {'total_GB':>9s}"]
+    for k, (n, fb, wb) in sorted(per.items(), key=lambda kv: -(kv[1][1] +
+                                                               kv[1][2])):
+        out.append(f"{k:52s} {n:6d} {fb / n / 1e9:9.4f} {wb / n / 1e9:9.4f}"
+                   f" {(fb + wb) / n / 1e9:9.4f}")
+    out.append("# launch sequence of the last factorization "
+               "(kernel, read_GB, write_GB)")
+    last = [i for i, (k, _, _) in enumerate(seq) if k == "fill_kernel"]
+    start = last[-1] if last else 0
+    for k, fb, wb in seq[start:]:
+        out.append(f"  {k:50s} {fb / 1e9:9.4f} {wb / 1e9:9.4f}")
+    return "\n".join(out)
+
+
+def main(argv):
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    if argv[1] == "trace":
+        print(trace(argv[2], argv[3], argv[4]))
+    elif argv[1] == "counters":
+        print(counters(argv[2], argv[3], argv[4], argv[5], root))
+    else:
+        raise SystemExit(__doc__)
+
+
+if __name__ == "__main__":
+    main(sys.argv)
