@@ -74,6 +74,7 @@ struct PassArgs {
 // ---------------------------------------------------------------- TSQR ---
 struct TsqrPlan {
   int s;
+  bool wave;       // one wave per chunk (s <= 16) instead of one workgroup
   int cr;          // rows per leaf chunk
   int fan;         // children per tree node (fan * s <= cr)
   int64_t nchunks;
@@ -161,6 +162,8 @@ struct EpiArgs {
   double* f1; double* f2;
   int f1_mode, f1_rows;   // F1 from (C1, T1), C1 having f1_rows rows
   int f2_mode, f2_rows;   // F2 from (C2, T2)
+  int fold12;             // the next pass runs both updates on the staged
+                          // columns: fold F1 into F2's rows [0, f1_rows + s)
   double* r; int64_t ldr;
   bcgs_info* info;
 };

@@ -221,6 +221,8 @@ struct Run {
 
   // f1/f2: which coefficient matrices the next pass needs (CoefMode) and
   // the number of rows of C1 / C2 they are built from
+  // With both f1 and f2 the next pass runs both block updates on the
+  // staged columns, so F1 is folded into F2 (fold_coefs).
   void epi(int mode, int j, bool has_e, bool chol_s, int f1 = COEF_NONE,
            int f1_rows = 0, int f2 = COEF_NONE, int f2_rows = 0) {
     EpiArgs e{};
@@ -232,6 +234,7 @@ struct Run {
     e.f1 = dws(p.off_f1); e.f2 = dws(p.off_f2);
     e.f1_mode = f1; e.f1_rows = f1_rows;
     e.f2_mode = f2; e.f2_rows = f2_rows;
+    e.fold12 = f1 != COEF_NONE && f2 != COEF_NONE;
     e.r = R; e.ldr = ldr; e.info = info;
     check(launch_epilogue(e, st));
   }

@@ -83,40 +83,61 @@ __device__ void store_tri(double* dst, int sp, int s, const double* src) {
 }
 
 // R(0:js, j-block) = C2 + C1 * T2 ;  R(j-block, j-block) = T1 * T2
-__device__ void assemble_r(const EpiArgs& a, const double* c1,
-                           const double* c2, const double* t1,
+// T1 (s x s row-major) is already in LDS; T2 is copied to sm.B.  One row of
+// C1 / C2 per thread: the row is loaded whole into registers (S > 0: the
+// block width is a compile-time constant and the loops unroll).
+template <int S>
+__device__ void assemble_r(EpiSmem& sm, const EpiArgs& a, const double* c1,
+                           const double* c2, const double* T1,
                            const double* t2) {
-  const int s = a.s, sp = a.sp, js = a.j * s;
-  for (int e = threadIdx.x; e < js * s; e += kThreads) {
-    const int i = e % js, c = e / js;
-    double acc = c2[i * sp + c];
-    for (int k = 0; k < s; ++k) acc += c1[i * sp + k] * t2[k * sp + c];
-    a.r[(size_t)(js + c) * a.ldr + i] = acc;
+  const int s = S ? S : a.s, sp = a.sp, js = a.j * s;
+  double* T2 = sm.B;
+  __syncthreads();
+  for (int e = threadIdx.x; e < s * s; e += kThreads)
+    T2[e] = t2[(e / s) * sp + e % s];
+  __syncthreads();
+  for (int i = threadIdx.x; i < js; i += kThreads) {
+    double y[S ? S : kMaxS];
+#pragma unroll
+    for (int k = 0; k < s; ++k) y[k] = c1[(size_t)i * sp + k];
+#pragma unroll
+    for (int c = 0; c < s; ++c) {
+      double acc = c2[(size_t)i * sp + c];
+#pragma unroll
+      for (int k = 0; k <= c; ++k) acc += y[k] * T2[k * s + c];
+      a.r[(size_t)(js + c) * a.ldr + i] = acc;
+    }
   }
   for (int e = threadIdx.x; e < s * s; e += kThreads) {
     const int i = e % s, c = e / s;
     double acc = 0.0;
     if (i <= c)
-      for (int k = i; k <= c; ++k) acc += t1[i * sp + k] * t2[k * sp + c];
+      for (int k = i; k <= c; ++k) acc += T1[i * s + k] * T2[k * s + c];
     a.r[(size_t)(js + c) * a.ldr + js + i] = acc;
   }
+  __syncthreads();
 }
 
 // F = [-C T^{-1}; T^{-1}] (scaled) or [-C; I] (unscaled), C with K rows.
 // T^{-1} by back substitution, one column per thread, in FP64.
+template <int S>
 __device__ void make_coef(EpiSmem& sm, double* F, const double* C, int K,
-                          const double* T, int scaled, int s, int sp) {
-  const int tid = threadIdx.x;
+                          const double* T, int scaled, int s_, int sp) {
+  const int tid = threadIdx.x, s = S ? S : s_;
   double* Ti = sm.B;                  // s x s row-major
+  double* Tl = sm.A;                  // LDS copy of T (s x s row-major)
   if (scaled) {
+    for (int e = tid; e < s * s; e += kThreads)
+      Tl[e] = T[(e / s) * sp + e % s];
+    __syncthreads();
     if (tid < s) {
       const int j = tid;
       for (int i = s - 1; i >= 0; --i) {
         double x = 0.0;
         if (i <= j) {
           x = (i == j) ? 1.0 : 0.0;
-          for (int k = i + 1; k <= j; ++k) x -= T[i * sp + k] * Ti[k * s + j];
-          x /= T[i * sp + i];
+          for (int k = i + 1; k <= j; ++k) x -= Tl[i * s + k] * Ti[k * s + j];
+          x /= Tl[i * s + i];
         }
         Ti[i * s + j] = x;
       }
@@ -126,17 +147,25 @@ __device__ void make_coef(EpiSmem& sm, double* F, const double* C, int K,
       Ti[e] = (e / s == e % s) ? 1.0 : 0.0;
   }
   __syncthreads();
-  for (int e = tid; e < K * sp; e += kThreads) {
-    const int i = e / sp, c = e % sp;
-    double v = 0.0;
-    if (c < s) {
-      if (scaled) {
-        for (int k = 0; k <= c; ++k) v -= C[i * sp + k] * Ti[k * s + c];
-      } else {
-        v = -C[i * sp + c];
+  // one row of C per thread: F(i, :) = -C(i, :) T^{-1}  (or -C(i, :))
+  for (int i = tid; i < K; i += kThreads) {
+    double cr[S ? S : kMaxS];
+#pragma unroll
+    for (int k = 0; k < s; ++k) cr[k] = C[(size_t)i * sp + k];
+    double* fr = F + (size_t)i * sp;
+#pragma unroll
+    for (int c = 0; c < (S ? (S + 15) / 16 * 16 : sp); ++c) {
+      double v = 0.0;
+      if (c < s) {
+        if (scaled) {
+#pragma unroll
+          for (int k = 0; k <= c; ++k) v -= cr[k] * Ti[k * s + c];
+        } else {
+          v = -cr[c];
+        }
       }
+      fr[c] = v;
     }
-    F[e] = v;
   }
   for (int e = tid; e < s * sp; e += kThreads) {
     const int i = e / sp, c = e % sp;
@@ -145,27 +174,62 @@ __device__ void make_coef(EpiSmem& sm, double* F, const double* C, int K,
   __syncthreads();
 }
 
+// The next pass forms B1 = [Q_{0:j-1} U_j] F1 (which replaces U_j) and
+// B2 = [Q_{0:j} X] F2 in one sweep over the staged columns [Q_{0:j-1} U_j X],
+// so B2 is rewritten on them: the rows of F2 that multiply the new block
+// (rows K1 .. K1+s-1, K1 = f1_rows) are replaced by F1 times those rows,
+//   F2'(0 : K1+s) = [F2(0 : K1); 0] + F1 F2(K1 : K1+s),
+// the same product in exact arithmetic.  One row of F1 per thread.
+template <int S>
+__device__ void fold_coefs(EpiSmem& sm, const EpiArgs& a) {
+  const int s = S ? S : a.s, sp = a.sp, K1 = a.f1_rows;
+  double* M = sm.A;                   // F2(K1 : K1+s), s x s row-major
+  for (int e = threadIdx.x; e < s * s; e += kThreads)
+    M[e] = a.f2[(size_t)(K1 + e / s) * sp + e % s];
+  __syncthreads();
+  for (int i = threadIdx.x; i < K1 + s; i += kThreads) {
+    double fr[S ? S : kMaxS];
+#pragma unroll
+    for (int k = 0; k < s; ++k) fr[k] = a.f1[(size_t)i * sp + k];
+    double* out = a.f2 + (size_t)i * sp;
+#pragma unroll
+    for (int c = 0; c < s; ++c) {
+      double v = i < K1 ? out[c] : 0.0;
+#pragma unroll
+      for (int k = 0; k < s; ++k) v += fr[k] * M[k * s + c];
+      out[c] = v;
+    }
+  }
+  __syncthreads();
+}
+
+template <int S>
 __device__ void make_coefs(EpiSmem& sm, const EpiArgs& a) {
   __syncthreads();
   if (a.f1_mode != COEF_NONE)
-    make_coef(sm, a.f1, a.c1, a.f1_rows, a.t1, a.f1_mode == COEF_SCALED,
+    make_coef<S>(sm, a.f1, a.c1, a.f1_rows, a.t1, a.f1_mode == COEF_SCALED,
               a.s, a.sp);
   if (a.f2_mode != COEF_NONE)
-    make_coef(sm, a.f2, a.c2, a.f2_rows, a.t2, a.f2_mode == COEF_SCALED,
+    make_coef<S>(sm, a.f2, a.c2, a.f2_rows, a.t2, a.f2_mode == COEF_SCALED,
               a.s, a.sp);
+  if (a.fold12 && a.f1_mode != COEF_NONE && a.f2_mode != COEF_NONE)
+    fold_coefs<S>(sm, a);
 }
 
+template <int S>
 __device__ void epilogue_body(EpiArgs a, EpiSmem& sm);
 
+template <int S>
 __global__ __launch_bounds__(kThreads) void epilogue_kernel(EpiArgs a) {
   __shared__ EpiSmem sm;
-  epilogue_body(a, sm);
-  make_coefs(sm, a);
+  epilogue_body<S>(a, sm);
+  make_coefs<S>(sm, a);
 }
 
+template <int S>
 __device__ void epilogue_body(EpiArgs a, EpiSmem& sm) {
   const int tid = threadIdx.x;
-  const int s = a.s, sp = a.sp, js = a.j * s;
+  const int s = S ? S : a.s, sp = a.sp, js = a.j * s;
 
   if (a.mode == EPI_S_ONLY || a.mode == EPI_Y_ONLY) {
     double* dst = a.mode == EPI_S_ONLY ? a.c2 : a.c1;
@@ -177,7 +241,9 @@ __device__ void epilogue_body(EpiArgs a, EpiSmem& sm) {
   }
 
   if (a.mode == EPI_R_ASSEMBLE) {
-    assemble_r(a, a.c1, a.c2, a.t1, a.t2);
+    for (int e = tid; e < s * s; e += kThreads)
+      sm.A[e] = a.t1[(e / s) * sp + e % s];
+    assemble_r<S>(sm, a, a.c1, a.c2, sm.A, a.t2);
     return;
   }
 
@@ -202,12 +268,49 @@ __device__ void epilogue_body(EpiArgs a, EpiSmem& sm) {
   // EPI_ONE_SYNC, after [Q_{0:j-1} U_j (E)]^T [U_j (E)]:
   //   Y = G(0:js, 0:s)     Omega = G(js:js+s, 0:s)
   //   Z = G(0:js, s:2s)    P = G(js:js+s, s:2s)    T = G(js+s:js+2s, s:2s)
+  // The three products over the js rows of Y and Z (Y^T Y, Y^T Z, Z^T Z)
+  // are accumulated together while row chunks of [Y Z] stream through LDS.
+  constexpr int kPer =
+      S ? (S * S + kThreads - 1) / kThreads : kMaxS * kMaxS / kThreads;
+  const int w2 = a.has_e ? 2 * s : s;
+  double yy[kPer], yz[kPer], zz[kPer];
+#pragma unroll
+  for (int t = 0; t < kPer; ++t) yy[t] = yz[t] = zz[t] = 0.0;
+  {
+    double* stg = sm.A;               // rows x w2, row-major
+    const int crows = (kMaxS * kMaxS) / w2;
+    for (int r0 = 0; r0 < js; r0 += crows) {
+      const int nr = min(crows, js - r0);
+      for (int e = tid; e < nr * w2; e += kThreads) {
+        const int c = e / nr, r = e % nr;
+        stg[r * w2 + c] = gram_at(a, r0 + r, c);
+      }
+      __syncthreads();
+#pragma unroll
+      for (int t = 0; t < kPer; ++t) {
+        const int e = tid + t * kThreads;
+        if (e < s * s) {
+          const int x = e / s, y = e % s;
+          double ay = yy[t], az = yz[t], bz = zz[t];
+          for (int r = 0; r < nr; ++r) {
+            const double* row = stg + r * w2;
+            ay += row[x] * row[y];
+            if (a.has_e) {
+              az += row[x] * row[s + y];
+              bz += row[s + x] * row[s + y];
+            }
+          }
+          yy[t] = ay; yz[t] = az; zz[t] = bz;
+        }
+      }
+      __syncthreads();
+    }
+  }
   // 1. Y_jj = chol(Omega - Y^T Y)
-  for (int e = tid; e < s * s; e += kThreads) {
-    const int x = e / s, y = e % s;
-    double acc = gram_at(a, js + x, y);
-    for (int k = 0; k < js; ++k) acc -= gram_at(a, k, x) * gram_at(a, k, y);
-    sm.A[e] = acc;
+#pragma unroll
+  for (int t = 0; t < kPer; ++t) {
+    const int e = tid + t * kThreads;
+    if (e < s * s) sm.A[e] = gram_at(a, js + e / s, e % s) - yy[t];
   }
   __syncthreads();
   chol_lds(sm, s, a.info, a.j, 1);
@@ -219,16 +322,14 @@ __device__ void epilogue_body(EpiArgs a, EpiSmem& sm) {
   }
   store_tri(a.t1, sp, s, sm.A);
   __syncthreads();
-  assemble_r(a, a.c1, a.c2, a.t1, a.t2);
-  __syncthreads();
+  assemble_r<S>(sm, a, a.c1, a.c2, sm.A, a.t2);
   if (!a.has_e) return;
   // 3. eq. (1): lower block L = Y_jj^{-T} (P - Y^T Z), forward substitution
   //    with Y_jj^T (lower triangular), one column per thread
-  for (int e = tid; e < s * s; e += kThreads) {
-    const int x = e / s, y = e % s;
-    double acc = gram_at(a, js + x, s + y);
-    for (int k = 0; k < js; ++k) acc -= gram_at(a, k, x) * gram_at(a, k, s + y);
-    sm.B[e] = acc;                    // M = P - Y^T Z (row-major)
+#pragma unroll
+  for (int t = 0; t < kPer; ++t) {
+    const int e = tid + t * kThreads;
+    if (e < s * s) sm.B[e] = gram_at(a, js + e / s, s + e % s) - yz[t];
   }
   __syncthreads();
   if (tid < s) {
@@ -248,21 +349,24 @@ __device__ void epilogue_body(EpiArgs a, EpiSmem& sm) {
     a.c2[e] = v;
   }
   if (!a.chol_s) return;
-  __syncthreads();
   // 4. S_{j+1,j+1} = chol(T - S^T S) with S = [Z; L]
-  double tmp[kMaxS * kMaxS / kThreads];
-  int nt = 0;
-  for (int e = tid; e < s * s; e += kThreads) {
-    const int x = e / s, y = e % s;
-    double acc = gram_at(a, js + s + x, s + y);
-    for (int k = 0; k < js; ++k)
-      acc -= gram_at(a, k, s + x) * gram_at(a, k, s + y);
-    for (int k = 0; k < s; ++k) acc -= sm.B[k * s + x] * sm.B[k * s + y];
-    tmp[nt++] = acc;
+  double tmp[kPer];
+#pragma unroll
+  for (int t = 0; t < kPer; ++t) {
+    const int e = tid + t * kThreads;
+    if (e < s * s) {
+      const int x = e / s, y = e % s;
+      double acc = gram_at(a, js + s + x, s + y) - zz[t];
+      for (int k = 0; k < s; ++k) acc -= sm.B[k * s + x] * sm.B[k * s + y];
+      tmp[t] = acc;
+    }
   }
   __syncthreads();
-  nt = 0;
-  for (int e = tid; e < s * s; e += kThreads) sm.A[e] = tmp[nt++];
+#pragma unroll
+  for (int t = 0; t < kPer; ++t) {
+    const int e = tid + t * kThreads;
+    if (e < s * s) sm.A[e] = tmp[t];
+  }
   __syncthreads();
   chol_lds(sm, s, a.info, a.j + 1, 0);
   store_tri(a.t2, sp, s, sm.A);
@@ -270,7 +374,15 @@ __device__ void epilogue_body(EpiArgs a, EpiSmem& sm) {
 
 hipError_t launch_epilogue(const EpiArgs& a, hipStream_t st) {
   prof_begin(BCGS_KERNEL_EPILOGUE, a.mode, 0.0, 0.0);
-  hipLaunchKernelGGL(epilogue_kernel, dim3(1), dim3(kThreads), 0, st, a);
+  switch (a.s) {
+#define EPI(S_) case S_: hipLaunchKernelGGL(epilogue_kernel<S_>, dim3(1), \
+                                            dim3(kThreads), 0, st, a); break;
+    EPI(4) EPI(8) EPI(16)
+#undef EPI
+    default:
+      hipLaunchKernelGGL(epilogue_kernel<0>, dim3(1), dim3(kThreads), 0, st,
+                         a);
+  }
   prof_end();
   return hipGetLastError();
 }

@@ -44,15 +44,24 @@ __device__ __forceinline__ const T* col_src(const PassArgs<T>& a, int c,
 // Block update of the tile columns [uc0, uc0 + s):
 //   out = tile[:, 0:uc0+s] * F        (MFMA over K = uc0 + s columns)
 // with F = [-C T^{-1}; T^{-1}] or [-C; I] (see common.h); the K range is
-// split over the waves and the partial products are summed in LDS.
+// split over the waves.  update_partials() leaves the partial products in
+// scr; update_finish() sums them into the tile and into dst.  When a pass
+// has two updates, both run on the staged columns before either result is
+// written back (the second one's coefficients already account for the
+// first, see fold_coefs in epilogue.hip).
+__device__ __forceinline__ int update_ksplit(int tr, int sp) {
+  const int nt = (tr >> 4) * (sp >> 4);
+  return nt >= kWaves ? 1 : kWaves / nt;
+}
+
 template <typename T>
-__device__ void block_update(const PassArgs<T>& a, double* tile, int trp,
-                             double* scr, int uc0, const double* __restrict__ F,
-                             T* dst, int64_t ldd, int64_t r0, int rows) {
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+__device__ void update_partials(const PassArgs<T>& a, const double* tile,
+                                int trp, double* scr, int uc0,
+                                const double* __restrict__ F) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int tr = a.tr, sp = a.sp, s = a.s;
   const int mb = tr >> 4, nb = sp >> 4, nt = mb * nb;
-  const int ksplit = nt >= kWaves ? 1 : kWaves / nt;
+  const int ksplit = update_ksplit(tr, sp);
   const int K = uc0 + s;
   const int ksteps = (K + 3) >> 2;
   const int kper = (ksteps + ksplit - 1) / ksplit;
@@ -77,8 +86,15 @@ __device__ void block_update(const PassArgs<T>& a, double* tile, int trp,
     for (int v = 0; v < 4; ++v)
       out[(rb * 16 + lk + 4 * v) * srow + cb * 16 + li] = acc[v];
   }
-  __syncthreads();
-  for (int e = tid; e < tr * s; e += kThreads) {
+}
+
+template <typename T>
+__device__ void update_finish(const PassArgs<T>& a, double* tile, int trp,
+                              const double* scr, int uc0, T* dst,
+                              int64_t ldd, int64_t r0, int rows) {
+  const int tr = a.tr, s = a.s, srow = a.sp + 1;
+  const int ksplit = update_ksplit(tr, a.sp);
+  for (int e = threadIdx.x; e < tr * s; e += kThreads) {
     const int r = e % tr, c = e / tr;
     double sum = 0.0;
     for (int ks = 0; ks < ksplit; ++ks)
@@ -86,7 +102,6 @@ __device__ void block_update(const PassArgs<T>& a, double* tile, int trp,
     tile[(uc0 + c) * trp + r] = sum;
     if (r < rows) dst[(int64_t)c * ldd + r0 + r] = static_cast<T>(sum);
   }
-  __syncthreads();
 }
 
 template <typename T, bool GRAM, int NTB, int MAXA>
@@ -132,13 +147,20 @@ __global__ __launch_bounds__(kThreads) void pass_kernel(PassArgs<T> a) {
       tile[c * trp + r] = v;
     }
     __syncthreads();
-    // 2-3. block updates
-    if (a.upd1)
-      block_update(a, tile, trp, scr, a.u1_c0, a.c1, a.dst1, a.ldd1, r0,
-                   rows);
-    if (a.upd2)
-      block_update(a, tile, trp, scr, a.u2_c0, a.c2, a.dst2, a.ldd2, r0,
-                   rows);
+    // 2-3. block updates, both on the staged columns
+    if (a.upd1 || a.upd2) {
+      double* scr2 = a.upd1 ? scr + (size_t)update_ksplit(tr, a.sp) * tr *
+                                        (a.sp + 1)
+                            : scr;
+      if (a.upd1) update_partials(a, tile, trp, scr, a.u1_c0, a.c1);
+      if (a.upd2) update_partials(a, tile, trp, scr2, a.u2_c0, a.c2);
+      __syncthreads();
+      if (a.upd1)
+        update_finish(a, tile, trp, scr, a.u1_c0, a.dst1, a.ldd1, r0, rows);
+      if (a.upd2)
+        update_finish(a, tile, trp, scr2, a.u2_c0, a.dst2, a.ldd2, r0, rows);
+      __syncthreads();
+    }
     // 4. Gram accumulation over this tile's rows
     if (GRAM) {
       for (int kk = 0; kk < tr; kk += 4) {
@@ -184,21 +206,35 @@ __global__ __launch_bounds__(kThreads) void pass_kernel(PassArgs<T> a) {
 // Fixed-order sum of the per-workgroup partial Gram matrices:
 // out[e] = sum_g partial[g][e], four interleaved partial sums per entry
 // combined in a fixed order.
-__global__ __launch_bounds__(kThreads) void gram_reduce_kernel(
+// Sum of the G per-workgroup partials, entry by entry, in a fixed order:
+// wave w of 16 adds partials w, w+16, ... into four interleaved running sums
+// (so four loads are in flight), and the 16 wave sums are added in wave
+// order.  The result depends only on G, never on timing.
+constexpr int kRedWaves = 16;
+
+__global__ __launch_bounds__(kRedWaves * 64) void gram_reduce_kernel(
     const double* __restrict__ partial, int G, int64_t elems,
     double* __restrict__ out) {
-  __shared__ double red[kWaves][64];
-  const int tid = threadIdx.x, lane = tid & 63, sub = tid >> 6;
+  __shared__ double red[kRedWaves][64];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int64_t e = (int64_t)blockIdx.x * 64 + lane;
-  double acc = 0.0;
-  if (e < elems)
-    for (int g = sub; g < G; g += kWaves) acc += partial[(size_t)g * elems + e];
-  red[sub][lane] = acc;
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+  if (e < elems) {
+    int g = w;
+    for (; g + 3 * kRedWaves < G; g += 4 * kRedWaves) {
+      a0 += partial[(size_t)g * elems + e];
+      a1 += partial[(size_t)(g + kRedWaves) * elems + e];
+      a2 += partial[(size_t)(g + 2 * kRedWaves) * elems + e];
+      a3 += partial[(size_t)(g + 3 * kRedWaves) * elems + e];
+    }
+    for (; g < G; g += kRedWaves) a0 += partial[(size_t)g * elems + e];
+  }
+  red[w][lane] = (a0 + a1) + (a2 + a3);
   __syncthreads();
-  if (sub == 0 && e < elems) {
+  if (w == 0 && e < elems) {
     double t = red[0][lane];
 #pragma unroll
-    for (int w = 1; w < kWaves; ++w) t += red[w][lane];
+    for (int i = 1; i < kRedWaves; ++i) t += red[i][lane];
     out[e] = t;
   }
 }
@@ -209,7 +245,7 @@ hipError_t launch_gram_reduce(const double* partial, int G, int64_t elems,
   prof_begin(BCGS_KERNEL_REDUCE, 0, 8.0 * elems * (G + 1),
              (double)elems * G);
   hipLaunchKernelGGL(gram_reduce_kernel, dim3((unsigned)blocks),
-                     dim3(kThreads), 0, st, partial, G, elems, out);
+                     dim3(kRedWaves * 64), 0, st, partial, G, elems, out);
   prof_end();
   return hipGetLastError();
 }
@@ -218,8 +254,9 @@ template <typename T>
 size_t pass_lds_bytes(const PassArgs<T>& a) {
   const int nt = (a.tr / 16) * (a.sp / 16);
   const int ksplit = nt >= kWaves ? 1 : kWaves / nt;
+  const int nupd = (a.upd1 ? 1 : 0) + (a.upd2 ? 1 : 0);
   size_t d = (size_t)a.ncols_p * (a.tr + 1) +
-             (size_t)ksplit * a.tr * (a.sp + 1);
+             (size_t)(nupd > 1 ? 2 : 1) * ksplit * a.tr * (a.sp + 1);
   return d * sizeof(double);
 }
 

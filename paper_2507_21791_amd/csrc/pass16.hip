@@ -1,15 +1,17 @@
 // Streaming pass for block widths s <= 16 (one 16-wide MFMA column block),
 // the shape of every large workload.  Same operation as pass.hip (block
-// updates of Alg. 1 / Alg. 2 fused with the tall-skinny Gram products),
-// organised for gfx950:
+// updates of Alg. 1 / Alg. 2 fused with the tall-skinny Gram products of one
+// synchronization point), organised for gfx950:
 //
-//  * NW = 4 waves per workgroup and two workgroups per CU when the tiles
-//    fit (one workgroup's MFMA work overlaps the other's serial phases),
-//    else NW = 8 and one workgroup per CU; the row range is walked in tiles
-//    of TR rows (16 or 32).
-//  * Two LDS tile buffers.  While tile t is being computed, tile t+1 is
-//    copied HBM -> LDS by direct-to-LDS loads (global_load_lds_dwordx4),
-//    so HBM streaming overlaps the MFMA work.
+//  * 4 waves per workgroup.  Either two workgroups per CU with two LDS tile
+//    buffers each, or one workgroup per CU with three or four buffers (a
+//    deeper copy pipeline for the widest passes).  The row range of a
+//    workgroup is walked in full tiles of TR rows (16, 32 or 64); a short
+//    last tile is staged synchronously after the loop.
+//  * Tiles arrive by direct-to-LDS copies (global_load_lds_dwordx4) issued
+//    NBUF - 1 tiles ahead.  Waiting for a tile counts only the copies issued
+//    after it (vector memory operations complete in issue order), so the
+//    copies of later tiles stay in flight.
 //  * LDS tile layout: column c occupies TR consecutive doubles; within a
 //    column the 16-byte granules (row pairs) are XOR-swizzled by a
 //    per-column key, which keeps both MFMA fragment patterns (16 columns x
@@ -17,11 +19,20 @@
 //    conflicts.
 //  * Block updates B <- [Q B] F (F = [-C T^{-1}; T^{-1}], see common.h):
 //    waves = (TR/16 row blocks) x (KG K-ranges); every wave keeps its slice
-//    of the coefficient fragments in registers for the whole kernel; both
-//    updates of a pass share the Q fragments; the K-range partial products
-//    are summed in LDS.
-//  * Gram A^T B: the 16x16 output tiles are dealt round-robin to the waves,
-//    which accumulate them in registers over the whole row range.
+//    of the coefficient fragments in registers for the whole kernel.  When
+//    a pass has two updates, both read the staged (old) columns (the second
+//    one's coefficients have the first one's folded in by the epilogue), so
+//    they share the fragment loads and their K-range partial sums are
+//    combined in one LDS round; the combine writes the results both to HBM
+//    (coalesced) and into the tile for the Gram.
+//  * Gram A^T B: the (A block, B block) pairs of 16x16 outputs are dealt
+//    round-robin to the waves (equal MFMA counts), which accumulate them in
+//    registers over the whole row range.
+#include <stdio.h>
+#include <stdlib.h>
+
+#include <algorithm>
+
 #include "common.h"
 
 namespace bcgs {
@@ -30,6 +41,8 @@ namespace p16 {
 
 typedef double v4d __attribute__((ext_vector_type(4)));
 constexpr int kMaxKF = 16;            // C fragments per update per wave
+constexpr int kNW = 4;                // waves per workgroup
+constexpr int kT = kNW * 64;
 
 __device__ __forceinline__ v4d mfma(double a, double b, v4d c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
@@ -48,6 +61,31 @@ __device__ __forceinline__ int at(int c, int r) {
   return c * TR + (((r >> 1) ^ swz<TR>(c)) << 1) + (r & 1);
 }
 
+// s_waitcnt vmcnt(n) (n <= 63), leaving the other counters alone
+#define P16_VM(n) (((n) & 15) | (((n) >> 4) << 14) | (7 << 4) | (15 << 8))
+__device__ __forceinline__ void wait_vm(int n) {
+  switch (n < 63 ? n : 63) {
+#define C4(b) case b: __builtin_amdgcn_s_waitcnt(P16_VM(b)); break;   \
+              case b + 1: __builtin_amdgcn_s_waitcnt(P16_VM(b + 1)); break; \
+              case b + 2: __builtin_amdgcn_s_waitcnt(P16_VM(b + 2)); break; \
+              case b + 3: __builtin_amdgcn_s_waitcnt(P16_VM(b + 3)); break;
+    C4(0) C4(4) C4(8) C4(12) C4(16) C4(20) C4(24) C4(28)
+    C4(32) C4(36) C4(40) C4(44) C4(48) C4(52) C4(56) C4(60)
+#undef C4
+  }
+}
+
+// Workgroup barrier for LDS traffic only.  __syncthreads() also waits for
+// every outstanding vector memory operation (vmcnt(0)), which would drain
+// the tile copies in flight; LDS visibility needs only lgkmcnt(0), and the
+// copies into LDS are waited for explicitly with wait_vm().
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_s_waitcnt((15) | (3 << 14) | (7 << 4) | (0 << 8));
+  asm volatile("" ::: "memory");
+  __builtin_amdgcn_s_barrier();
+  asm volatile("" ::: "memory");
+}
+
 struct Args {
   int64_t m;
   int s, ncols, ncols_p;
@@ -55,7 +93,6 @@ struct Args {
   const double* q; int64_t ldq; int nq;
   const double* f; int64_t ldf; int fcols;
   const double* e; int64_t lde; int ecols;
-  int dma;                       // all leading dimensions even: 16B loads
   int upd1, u1_c0; const double* c1; double* dst1; int64_t ldd1;
   int upd2, u2_c0; const double* c2; double* dst2; int64_t ldd2;
   int gram, ga_p, gb0, gbn_p, skip_a0, skip_b1;
@@ -72,31 +109,10 @@ __device__ __forceinline__ const double* col_ptr(const Args& a, int c,
   return a.e + (int64_t)c * a.lde;
 }
 
-// Issue the direct-to-LDS copy of a full tile (rows r0 .. r0+TR-1).
-template <int NW, int TR>
-__device__ __forceinline__ void tile_dma(const Args& a, double* buf,
-                                         int64_t r0) {
-  constexpr int kColsPerInst = 1024 / (TR * 8);     // 4 (TR=32) or 8 (16)
-  constexpr int kGran = TR / 2;                      // granules per column
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int ninst = (a.ncols + kColsPerInst - 1) / kColsPerInst;
-  for (int ins = wave; ins < ninst; ins += NW) {
-    const int c = ins * kColsPerInst + lane / kGran;
-    const int g = lane % kGran;
-    double* dst = buf + ins * kColsPerInst * TR;     // wave-uniform
-    if (c < a.ncols) {
-      int64_t ld;
-      const double* src = col_ptr(a, c, &ld);
-      const int rr = (g ^ swz<TR>(c)) << 1;
-      __builtin_amdgcn_global_load_lds(src + r0 + rr, dst, 16, 0, 0);
-    }
-  }
-}
-
-// Synchronous staging (tail tiles, odd leading dimensions): zero past m.
-template <int NW, int TR>
+// Synchronous staging of a short last tile: zero past the row count.
+template <int TR>
 __device__ void tile_sync(const Args& a, double* buf, int64_t r0, int rows) {
-  for (int idx = threadIdx.x; idx < a.ncols * TR; idx += NW * 64) {
+  for (int idx = threadIdx.x; idx < a.ncols * TR; idx += kT) {
     const int c = idx / TR, r = idx % TR;
     double v = 0.0;
     if (r < rows) {
@@ -108,15 +124,16 @@ __device__ void tile_sync(const Args& a, double* buf, int64_t r0, int rows) {
   }
 }
 
-// Sum the K-range partial products of one block update into the tile
-// columns [uc0, uc0 + s).  scr: [KG][TR][17] doubles.
-template <int NW, int TR, int KG>
+// Sum the K-range partial products of one block update (scr: [KG][TR][17])
+// into the tile columns [uc0, uc0 + s) and into dst (rows < rows).
+template <int TR, int KG>
 __device__ __forceinline__ void combine(const Args& a, double* tile,
-                                        const double* scr, int uc0) {
-  const int s = a.s;
-  for (int t = threadIdx.x; t < TR * 16; t += NW * 64) {
-    const int r = t >> 4, c = t & 15;
-    if (c >= s) continue;
+                                        const double* scr, int uc0,
+                                        double* dst, int64_t ldd, int64_t r0,
+                                        int rows) {
+  for (int t = threadIdx.x; t < TR * 16; t += kT) {
+    const int r = t % TR, c = t / TR;
+    if (c >= a.s) continue;
     double part[KG];
 #pragma unroll
     for (int k = 0; k < KG; ++k) part[k] = scr[(k * TR + r) * 17 + c];
@@ -124,254 +141,347 @@ __device__ __forceinline__ void combine(const Args& a, double* tile,
 #pragma unroll
     for (int k = 0; k < KG; ++k) sum += part[k];
     tile[at<TR>(uc0 + c, r)] = sum;
+    if (r < rows) dst[(int64_t)c * ldd + r0 + r] = sum;
   }
 }
 
-// Copy an updated block (tile columns uc0..uc0+s-1) to HBM, coalesced.
-template <int NW, int TR>
-__device__ __forceinline__ void store_block(const Args& a, const double* tile,
-                                            int uc0, double* dst, int64_t ldd,
-                                            int64_t r0, int rows) {
-  for (int idx = threadIdx.x; idx < a.s * TR; idx += NW * 64) {
-    const int c = idx / TR, r = idx % TR;
-    if (r < rows) dst[(int64_t)c * ldd + r0 + r] = tile[at<TR>(uc0 + c, r)];
-  }
-}
+// One workgroup per row range.  TR tile rows; NBUF tile buffers of CAP
+// columns, each its own LDS object; PC workgroups per CU; MAXP Gram pairs
+// per wave; NTB B blocks.  With one workgroup per CU there is LDS room for
+// both updates' partial sums.
+//
+// Copy pipeline.  Each wave issues exactly IPW copy instructions per tile
+// (waves with fewer instructions repeat their last one, lanes past the last
+// column copy a valid column into the zero-weight padding), so the number
+// of copies in flight is a compile-time constant: before tile t is read,
+// vmcnt((NBUF - 2) IPW) leaves the copies of the next NBUF - 2 tiles in
+// flight.  The tile loop is unrolled by NBUF so that every LDS access names
+// its buffer statically; the compiler then sees that the copies in flight
+// target other buffers and inserts no waits of its own.
+template <int TR, int NBUF, int CAP, int PC, int MAXP, bool GRAM, int NTB>
+struct Kernel {
+  static constexpr bool SCR2 = PC == 1;
+  static constexpr int MB = TR / 16;          // row blocks per tile
+  static constexpr int KG = kNW / MB;         // K ranges per update
+  static constexpr int kTail = (4 + KG - 1) / KG;
+  static constexpr int CPI = 1024 / (TR * 8); // columns per copy instruction
+  static constexpr int IPW = ((CAP + CPI - 1) / CPI + kNW - 1) / kNW;
+  static constexpr int TE = CAP * TR;         // doubles per buffer
+  static_assert(CAP % CPI == 0, "buffer holds whole copy instructions");
 
-// two waves per SIMD: two 4-wave workgroups, or one 8-wave workgroup, per CU
-template <int NW, int TR, int MAXA, bool GRAM, int NTB>
-__global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(2)))
-void pass16_kernel(Args a) {
-  constexpr int kT = NW * 64;
-  constexpr int MB = TR / 16;         // row blocks per tile
-  constexpr int KG = NW / MB;         // K ranges per update
-  extern __shared__ double lds[];
-  const int tile_elems = a.ncols_p * TR;
-  double* buf0 = lds;
-  double* buf1 = lds + tile_elems;
-  double* scr = buf1 + tile_elems;                  // KG * TR * 17
+  // register-resident state of one wave
+  struct State {
+    double c1f[kMaxKF], c2f[kMaxKF];   // shared K-steps (both updates)
+    double c2o[kTail];                 // update 2, steps over its own block
+    int kb, ke, nks2, sq;
+    int mb, kg;
+    v4d acc[MAXP];
+    int npairs;
+  };
 
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int li = lane & 15, lk = lane >> 4;
-  const int mb = wave % MB, kg = wave / MB;
-  const int64_t g = blockIdx.x;
-  const int64_t row_begin = g * a.rows_per_wg;
-  const int64_t row_end = min(a.m, row_begin + a.rows_per_wg);
-
-  // ---- prologue: coefficient fragments --------------------------------
-  // K-steps (4 columns each) of update 1: [0, nks1) over Q_{1:k-1} (shared
-  // with update 2) and [nks1, nks1 + sq) over its own block; of update 2:
-  // [0, nks1) shared, [nks1, nks2) over the block update 1 rewrites (after
-  // it), and [nks2, nks2 + sq) over its own block F.  Without update 1,
-  // update 2's steps [0, nks2) are all "shared".
-  const int s = a.s;
-  const int sq = s / 4;
-  const int nks1 = a.upd1 ? a.u1_c0 / 4 : 0;
-  const int nks2 = a.upd2 ? a.u2_c0 / 4 : 0;
-  const int shared = a.upd1 ? nks1 : nks2;
-  const int per = (shared + KG - 1) / KG;
-  const int kb = kg * per, ke = min(shared, kb + per);
-  double c1f[kMaxKF], c2f[kMaxKF];
+  // direct-to-LDS copy of the full tile at rows r0 .. r0+TR-1
+  static __device__ __forceinline__ void dma(const Args& a, double* buf,
+                                             int64_t r0) {
+    constexpr int kGran = TR / 2;                    // granules per column
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int ninst = (a.ncols + CPI - 1) / CPI;
 #pragma unroll
-  for (int i = 0; i < kMaxKF; ++i) {
-    const int k = kb + i;
-    c1f[i] = 0.0;
-    c2f[i] = 0.0;
-    if (k < ke) {
-      const int row = 4 * k + lk;
-      if (a.upd1) c1f[i] = a.c1[row * 16 + li];
-      if (a.upd2) c2f[i] = a.c2[row * 16 + li];
+    for (int i = 0; i < IPW; ++i) {
+      const int ins = min(wave + kNW * i, ninst - 1);
+      const int c = ins * CPI + lane / kGran;
+      const int g = lane % kGran;
+      int64_t ld;
+      const double* src = col_ptr(a, min(c, a.ncols - 1), &ld);
+      const int rr = (g ^ swz<TR>(c)) << 1;
+      __builtin_amdgcn_global_load_lds(src + r0 + rr, buf + ins * CPI * TR,
+                                       16, 0, 0);
     }
   }
-  // per-block steps, step t < sq goes to K range t % KG
-  constexpr int kTail = (4 + KG - 1) / KG;
-  const int ntail = (a.upd1 && a.upd2) ? sq : 0;   // update 2 over new block
-  double c1o[kTail], c2o[kTail], c2t[kTail];
-#pragma unroll
-  for (int u = 0; u < kTail; ++u) {
-    const int t = kg + KG * u;
-    c1o[u] = (a.upd1 && t < sq) ? a.c1[(4 * (nks1 + t) + lk) * 16 + li] : 0.0;
-    c2o[u] = (a.upd2 && t < sq) ? a.c2[(4 * (nks2 + t) + lk) * 16 + li] : 0.0;
-    c2t[u] = t < ntail ? a.c2[(4 * (nks1 + t) + lk) * 16 + li] : 0.0;
-  }
-  for (int idx = a.ncols * TR + tid; idx < tile_elems; idx += kT) {
-    buf0[idx] = 0.0;
-    buf1[idx] = 0.0;
-  }
 
-  // ---- Gram: this wave owns A blocks ta = wave, wave + NW, ... and all
-  //      NTB B blocks, so B fragments are shared across its A blocks ----
-  v4d acc[MAXA][NTB];
-  const int nta = a.ga_p >> 4;
-#pragma unroll
-  for (int i = 0; i < MAXA; ++i)
-#pragma unroll
-    for (int b = 0; b < NTB; ++b) acc[i][b] = v4d{0.0, 0.0, 0.0, 0.0};
-
-  // ---- tile loop ---------------------------------------------------------
-  bool prefetched = false;
-  int it = 0;
-  if (row_begin < row_end && a.dma && row_begin + TR <= row_end) {
-    tile_dma<NW, TR>(a, buf0, row_begin);
-    prefetched = true;
-  }
-  for (int64_t r0 = row_begin; r0 < row_end; r0 += TR, ++it) {
-    double* tile = (it & 1) ? buf1 : buf0;
-    double* next = (it & 1) ? buf0 : buf1;
-    const int rows = (int)min((int64_t)TR, row_end - r0);
-    if (!prefetched) tile_sync<NW, TR>(a, tile, r0, rows);
-    __builtin_amdgcn_s_waitcnt(0);
-    __syncthreads();
-    // prefetch the next tile while this one is computed
-    const int64_t r1 = r0 + TR;
-    prefetched = false;
-    if (a.dma && r1 + TR <= row_end) {
-      tile_dma<NW, TR>(a, next, r1);
-      prefetched = true;
-    }
-
+  static __device__ __forceinline__ void process(const Args& a, State& S,
+                                                 double* tile, double* scr,
+                                                 int64_t r0, int rows) {
+    const int lane = threadIdx.x & 63;
+    const int li = lane & 15, lk = lane >> 4;
     // ---- block updates ----
     if (a.upd1 || a.upd2) {
-      // K-steps in uniform chunks of 4; inside a chunk the four Q fragment
-      // loads are issued first, K-steps past ke read a valid address and
+      // K-steps in uniform chunks of 4; inside a chunk the four fragment
+      // loads are issued first; K-steps past ke read a valid address and
       // meet zero coefficient fragments, so no lane-divergent branches
       v4d acc1 = {0.0, 0.0, 0.0, 0.0}, acc2 = {0.0, 0.0, 0.0, 0.0};
       v4d acc1b = {0.0, 0.0, 0.0, 0.0}, acc2b = {0.0, 0.0, 0.0, 0.0};
-      const int kcl = max(kb, min(ke, shared) - 1);
+      const int kcl = max(S.kb, S.ke - 1);
+      const int row = S.mb * 16 + li;
 #pragma unroll
       for (int q = 0; q < kMaxKF / 4; ++q) {
-        if (4 * q >= ke - kb) break;
+        if (4 * q >= S.ke - S.kb) break;
         double av[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-          const int k = min(kb + 4 * q + u, kcl);
-          av[u] = tile[at<TR>(4 * k + lk, mb * 16 + li)];
+          const int k = min(S.kb + 4 * q + u, kcl);
+          av[u] = tile[at<TR>(4 * k + lk, row)];
         }
 #pragma unroll
         for (int u = 0; u < 4; u += 2) {
-          if (a.upd1) acc1 = mfma(av[u], c1f[4 * q + u], acc1);
-          if (a.upd2) acc2 = mfma(av[u], c2f[4 * q + u], acc2);
-          if (a.upd1) acc1b = mfma(av[u + 1], c1f[4 * q + u + 1], acc1b);
-          if (a.upd2) acc2b = mfma(av[u + 1], c2f[4 * q + u + 1], acc2b);
-        }
-      }
-      // own-block steps (independent of update 1's result)
-#pragma unroll
-      for (int u = 0; u < kTail; ++u) {
-        const int t = kg + KG * u;
-        if (t < sq) {
-          if (a.upd1)
-            acc1b = mfma(tile[at<TR>(4 * (nks1 + t) + lk, mb * 16 + li)],
-                         c1o[u], acc1b);
-          if (a.upd2)
-            acc2b = mfma(tile[at<TR>(4 * (nks2 + t) + lk, mb * 16 + li)],
-                         c2o[u], acc2b);
-        }
-      }
-      acc1 += acc1b;
-      acc2 += acc2b;
-      if (a.upd1) {
-#pragma unroll
-        for (int v = 0; v < 4; ++v)
-          scr[(kg * TR + mb * 16 + lk + 4 * v) * 17 + li] = acc1[v];
-        __syncthreads();
-        combine<NW, TR, KG>(a, tile, scr, a.u1_c0);
-        __syncthreads();
-        store_block<NW, TR>(a, tile, a.u1_c0, a.dst1, a.ldd1, r0, rows);
-        // update 2 over the block update 1 just formed
-#pragma unroll
-        for (int u = 0; u < kTail; ++u) {
-          const int t = kg + KG * u;
-          if (t < ntail)
-            acc2 = mfma(tile[at<TR>(4 * (nks1 + t) + lk, mb * 16 + li)],
-                        c2t[u], acc2);
+          if (a.upd1) acc1 = mfma(av[u], S.c1f[4 * q + u], acc1);
+          if (a.upd2) acc2 = mfma(av[u], S.c2f[4 * q + u], acc2);
+          if (a.upd1) acc1b = mfma(av[u + 1], S.c1f[4 * q + u + 1], acc1b);
+          if (a.upd2) acc2b = mfma(av[u + 1], S.c2f[4 * q + u + 1], acc2b);
         }
       }
       if (a.upd2) {
 #pragma unroll
+        for (int u = 0; u < kTail; ++u) {
+          const int t = S.kg + KG * u;
+          if (t < S.sq)
+            acc2b = mfma(tile[at<TR>(4 * (S.nks2 + t) + lk, row)], S.c2o[u],
+                         acc2b);
+        }
+      }
+      acc1 += acc1b;
+      acc2 += acc2b;
+      double* scr1 = scr;
+      double* scr2 = SCR2 ? scr + KG * TR * 17 : scr;
+      if (a.upd1) {
+#pragma unroll
         for (int v = 0; v < 4; ++v)
-          scr[(kg * TR + mb * 16 + lk + 4 * v) * 17 + li] = acc2[v];
-        __syncthreads();
-        combine<NW, TR, KG>(a, tile, scr, a.u2_c0);
-        __syncthreads();
-        store_block<NW, TR>(a, tile, a.u2_c0, a.dst2, a.ldd2, r0, rows);
+          scr1[(S.kg * TR + S.mb * 16 + lk + 4 * v) * 17 + li] = acc1[v];
+      }
+      if (a.upd2 && (SCR2 || !a.upd1)) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+          scr2[(S.kg * TR + S.mb * 16 + lk + 4 * v) * 17 + li] = acc2[v];
+      }
+      lds_barrier();
+      if (a.upd1)
+        combine<TR, KG>(a, tile, scr1, a.u1_c0, a.dst1, a.ldd1, r0, rows);
+      if (a.upd2 && (SCR2 || !a.upd1))
+        combine<TR, KG>(a, tile, scr2, a.u2_c0, a.dst2, a.ldd2, r0, rows);
+      lds_barrier();
+      if (!SCR2 && a.upd1 && a.upd2) {
+        // one partial-sum area: the second update's round
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+          scr[(S.kg * TR + S.mb * 16 + lk + 4 * v) * 17 + li] = acc2[v];
+        lds_barrier();
+        combine<TR, KG>(a, tile, scr, a.u2_c0, a.dst2, a.ldd2, r0, rows);
+        lds_barrier();
       }
     }
-
-    // ---- Gram accumulation: two MFMA K-steps per 16-byte LDS load (lane
-    //      group lk takes rows kk + 2 lk and kk + 2 lk + 1) ----
+    // ---- Gram: two MFMA K-steps per 16-byte LDS load (lane group lk
+    //      takes rows kk + 2 lk and kk + 2 lk + 1).  Pair i of this wave is
+    //      p = wave + 4 i; since 4 is a multiple of NTB, every pair of a
+    //      wave uses the same B block, wave % NTB. ----
     if (GRAM) {
+      const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+      const int bcol = a.gb0 + (wave % NTB) * 16 + li;
 #pragma unroll
       for (int kk = 0; kk < TR; kk += 8) {
         const int r = kk + 2 * lk;
-        double2 bf[NTB], af[MAXA];
+        const double2 bf =
+            *reinterpret_cast<const double2*>(tile + at<TR>(bcol, r));
 #pragma unroll
-        for (int b = 0; b < NTB; ++b)
-          bf[b] = *reinterpret_cast<const double2*>(
-              tile + at<TR>(a.gb0 + b * 16 + li, r));
-#pragma unroll
-        for (int i = 0; i < MAXA; ++i) {
-          // A blocks past the last are computed on a valid block and
-          // never stored
-          const int ta = min(wave + NW * i, nta - 1);
-          af[i] = *reinterpret_cast<const double2*>(
-              tile + at<TR>(ta * 16 + li, r));
+        for (int i = 0; i < MAXP; ++i) {
+          const int p = wave + kNW * i;
+          if (p < S.npairs) {          // wave-uniform
+            const double2 af = *reinterpret_cast<const double2*>(
+                tile + at<TR>((p / NTB) * 16 + li, r));
+            S.acc[i] = mfma(af.x, bf.x, S.acc[i]);
+            S.acc[i] = mfma(af.y, bf.y, S.acc[i]);
+          }
         }
-#pragma unroll
-        for (int i = 0; i < MAXA; ++i)
-#pragma unroll
-          for (int b = 0; b < NTB; ++b)
-            acc[i][b] = mfma(af[i].x, bf[b].x, acc[i][b]);
-#pragma unroll
-        for (int i = 0; i < MAXA; ++i)
-#pragma unroll
-          for (int b = 0; b < NTB; ++b)
-            acc[i][b] = mfma(af[i].y, bf[b].y, acc[i][b]);
       }
     }
   }
-  __builtin_amdgcn_s_waitcnt(0);
 
-  if (GRAM) {
-    double* out = a.partial + (size_t)g * a.ga_p * a.gbn_p;
+  // pipelined step on buffer I: tile t is waited for, the copy of tile
+  // t + NBUF - 1 goes into the buffer tile t - 1 used, tile t is computed
+  template <int I>
+  static __device__ __forceinline__ void step(const Args& a, State& S,
+                                              double* const (&bufs)[4],
+                                              double* scr, int64_t row0,
+                                              int64_t t) {
+    __builtin_amdgcn_s_waitcnt(P16_VM((NBUF - 2) * IPW));
+    lds_barrier();
+    dma(a, bufs[(I + NBUF - 1) % NBUF], row0 + (t + NBUF - 1) * TR);
+    process(a, S, bufs[I], scr, row0 + t * TR, TR);
+  }
+
+  static __device__ void run(const Args& a) {
+    __shared__ double b0[TE];
+    __shared__ double b1[TE];
+    __shared__ double b2[NBUF > 2 ? TE : 1];
+    __shared__ double b3[NBUF > 3 ? TE : 1];
+    __shared__ double scr[(SCR2 ? 2 : 1) * 64 * 17];
+    double* const bufs[4] = {b0, b1, b2, b3};
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform
+    const int li = lane & 15, lk = lane >> 4;
+    const int64_t g = blockIdx.x;
+    const int64_t row_begin = g * a.rows_per_wg;
+    const int64_t row_end = min(a.m, row_begin + a.rows_per_wg);
+
+    State S;
+    S.mb = wave % MB;
+    S.kg = wave / MB;
+    // ---- coefficient fragments.  Update 1 runs over the staged columns
+    // [0, u1_c0 + s); update 2 over [0, u2_c0) plus its own block F.  With
+    // both updates u2_c0 = u1_c0 + s, so the two share all K-steps except
+    // update 2's own block. ----
+    const int s = a.s;
+    S.sq = s / 4;
+    const int nks1 = a.upd1 ? (a.u1_c0 + s) / 4 : 0;
+    S.nks2 = a.upd2 ? a.u2_c0 / 4 : 0;
+    const int shared = max(nks1, S.nks2);
+    const int per = (shared + KG - 1) / KG;
+    S.kb = S.kg * per;
+    S.ke = min(shared, S.kb + per);
 #pragma unroll
-    for (int i = 0; i < MAXA; ++i) {
-      const int ta = wave + NW * i;
-      if (ta >= nta) continue;
+    for (int i = 0; i < kMaxKF; ++i) {
+      const int k = S.kb + i;
+      const int row = 4 * k + lk;
+      S.c1f[i] = (k < S.ke && k < nks1) ? a.c1[row * 16 + li] : 0.0;
+      S.c2f[i] = (k < S.ke && k < S.nks2) ? a.c2[row * 16 + li] : 0.0;
+    }
 #pragma unroll
-      for (int b = 0; b < NTB; ++b) {
-        if (ta * 16 >= a.skip_a0 && b * 16 + 16 <= a.skip_b1) continue;
+    for (int u = 0; u < kTail; ++u) {
+      const int t = S.kg + KG * u;
+      S.c2o[u] = (a.upd2 && t < S.sq)
+                     ? a.c2[(4 * (S.nks2 + t) + lk) * 16 + li] : 0.0;
+    }
+    // ---- Gram pairs p = wave + 4 i, p = (A block) * NTB + (B block) ----
+    const int nta = a.ga_p >> 4;
+    S.npairs = GRAM ? nta * NTB : 1;
+#pragma unroll
+    for (int i = 0; i < MAXP; ++i) S.acc[i] = v4d{0.0, 0.0, 0.0, 0.0};
+    // the fragment loads above complete here, so no wait for them is left
+    // pending inside the tile loop, where it would drain the copies
+    __builtin_amdgcn_s_waitcnt(0);
+    // zero the columns past the copied ones (multiplied by zero weights
+    // in the updates; their Gram entries are not read)
+    for (int idx = a.ncols_p * TR + tid; idx < TE; idx += kT) {
+      b0[idx] = 0.0;
+      b1[idx] = 0.0;
+      if (NBUF > 2) b2[idx] = 0.0;
+      if (NBUF > 3) b3[idx] = 0.0;
+    }
+
+    // ---- full tiles ----
+    const int64_t nfull = row_end > row_begin ? (row_end - row_begin) / TR : 0;
+    int64_t t = 0, issued = 0;
+    if (nfull >= 2 * NBUF - 1) {
+#pragma unroll
+      for (int i = 0; i < NBUF - 1; ++i)
+        dma(a, bufs[i], row_begin + i * TR);
+      for (; t + 2 * NBUF - 2 < nfull; t += NBUF) {
+        step<0>(a, S, bufs, scr, row_begin, t);
+        step<1>(a, S, bufs, scr, row_begin, t + 1);
+        if constexpr (NBUF > 2) step<2>(a, S, bufs, scr, row_begin, t + 2);
+        if constexpr (NBUF > 3) step<3>(a, S, bufs, scr, row_begin, t + 3);
+      }
+      issued = t + NBUF - 1;
+    }
+    // the last few tiles one at a time, without overlap
+    for (; t < nfull; ++t) {
+      const int bi = (int)(t % NBUF);
+      double* tile = bi == 0 ? b0 : bi == 1 ? b1 : bi == 2 ? b2 : b3;
+      if (t >= issued) dma(a, tile, row_begin + t * TR);
+      __builtin_amdgcn_s_waitcnt(0);
+      lds_barrier();
+      process(a, S, tile, scr, row_begin + t * TR, TR);
+    }
+    // ---- short last tile ----
+    const int64_t rt = row_begin + nfull * TR;
+    if (rt < row_end) {
+      __builtin_amdgcn_s_waitcnt(0);
+      lds_barrier();
+      tile_sync<TR>(a, b0, rt, (int)(row_end - rt));
+      lds_barrier();
+      process(a, S, b0, scr, rt, (int)(row_end - rt));
+    }
+
+    if (GRAM) {
+      double* out = a.partial + (size_t)g * a.ga_p * a.gbn_p;
+#pragma unroll
+      for (int i = 0; i < MAXP; ++i) {
+        const int p = wave + kNW * i;
+        if (p >= S.npairs) continue;
+        const int ta = (p / NTB) * 16, b = p % NTB;
+        if (ta >= a.skip_a0 && b * 16 + 16 <= a.skip_b1) continue;
 #pragma unroll
         for (int v = 0; v < 4; ++v)
-          out[(size_t)(b * 16 + li) * a.ga_p + ta * 16 + lk + 4 * v] =
-              acc[i][b][v];
+          out[(size_t)(b * 16 + li) * a.ga_p + ta + lk + 4 * v] = S.acc[i][v];
       }
     }
   }
+};
+
+// two workgroups per CU: at most 256 registers per lane
+template <int TR, int NBUF, int CAP, int MAXP, bool GRAM, int NTB>
+__global__ __launch_bounds__(kT) __attribute__((amdgpu_waves_per_eu(2)))
+void pass16_kernel(Args a) {
+  Kernel<TR, NBUF, CAP, 2, MAXP, GRAM, NTB>::run(a);
 }
 
-template <int NW, int TR, int MAXA, bool GRAM, int NTB>
-static hipError_t go(const Args& a, int G, size_t lds, hipStream_t st,
-                     int* tag) {
-  auto kern = pass16_kernel<NW, TR, MAXA, GRAM, NTB>;
-  static bool attr = false;
-  if (!attr) {
-    (void)hipFuncSetAttribute((const void*)kern,
-                              hipFuncAttributeMaxDynamicSharedMemorySize,
-                              160 * 1024);
-    attr = true;
-  }
-  // 1NWTTMMG: waves, tile rows, A blocks per wave, B blocks (0: no Gram)
-  *tag = 10000000 + NW * 1000000 + TR * 1000 + MAXA * 10 + (GRAM ? NTB : 0);
-  hipLaunchKernelGGL(kern, dim3((unsigned)G), dim3(NW * 64), lds, st, a);
+// one workgroup per CU: the register file of the SIMD to itself
+template <int TR, int NBUF, int CAP, int MAXP, bool GRAM, int NTB>
+__global__ __launch_bounds__(kT) __attribute__((amdgpu_waves_per_eu(1)))
+void pass16_deep_kernel(Args a) {
+  Kernel<TR, NBUF, CAP, 1, MAXP, GRAM, NTB>::run(a);
+}
+
+template <int TR, int NBUF, int CAP, int PC, int MAXP, bool GRAM, int NTB>
+static hipError_t go(const Args& a, int G, hipStream_t st, int* tag) {
+  // 1 B TT PP N: tile buffers (+4 for one workgroup per CU), tile rows,
+  // Gram pairs per wave, B blocks (0: no Gram)
+  *tag = 10000000 + (NBUF + (PC == 1 ? 4 : 0)) * 1000000 + TR * 1000 +
+         MAXP * 10 + (GRAM ? NTB : 0);
+  if constexpr (PC == 2)
+    hipLaunchKernelGGL((pass16_kernel<TR, NBUF, CAP, MAXP, GRAM, NTB>),
+                       dim3((unsigned)G), dim3(kT), 0, st, a);
+  else
+    hipLaunchKernelGGL((pass16_deep_kernel<TR, NBUF, CAP, MAXP, GRAM, NTB>),
+                       dim3((unsigned)G), dim3(kT), 0, st, a);
   return hipGetLastError();
+}
+
+// (tile rows, buffers, column capacity, workgroups per CU)
+struct Shape { int tr, nbuf, cap, per_cu; };
+
+// in order of preference; BCGS_PASS16_SHAPE=<index> forces one (tuning).
+// launch_pass16's switch instantiates the same list, entry by entry.
+constexpr Shape kShapes[] = {
+    {64, 2, 64, 2}, {32, 2, 128, 2}, {16, 2, 272, 2},
+    {16, 4, 272, 1}, {64, 4, 64, 1}, {32, 4, 128, 1}};
+constexpr int kNShapes = sizeof(kShapes) / sizeof(kShapes[0]);
+
+static bool shape_fits(const Shape& sh, int ncols_p, int shared_ksteps,
+                       int maxp) {
+  const int kg = kNW / (sh.tr / 16);
+  if ((shared_ksteps + kg - 1) / kg > kMaxKF) return false;
+  return ncols_p <= sh.cap;
+}
+
+template <int TR, int NBUF, int CAP, int PC>
+static hipError_t go_shape(const Args& a, int G, bool gram, int ntb,
+                           int maxp, hipStream_t st, int* tag) {
+  if (!gram) return go<TR, NBUF, CAP, PC, 1, false, 1>(a, G, st, tag);
+  if (ntb == 1) {
+    if (maxp <= 2) return go<TR, NBUF, CAP, PC, 2, true, 1>(a, G, st, tag);
+    if (maxp <= 5) return go<TR, NBUF, CAP, PC, 5, true, 1>(a, G, st, tag);
+    return go<TR, NBUF, CAP, PC, 10, true, 1>(a, G, st, tag);
+  }
+  if (maxp <= 2) return go<TR, NBUF, CAP, PC, 2, true, 2>(a, G, st, tag);
+  if (maxp <= 5) return go<TR, NBUF, CAP, PC, 5, true, 2>(a, G, st, tag);
+  return go<TR, NBUF, CAP, PC, 10, true, 2>(a, G, st, tag);
 }
 
 }  // namespace p16
 
 size_t pass16_lds_bytes(int ncols_p, int tr, int nw) {
-  const int kg = nw / (tr / 16);
-  return ((size_t)2 * ncols_p * tr + (size_t)kg * tr * 17) * sizeof(double);
+  (void)nw;
+  return ((size_t)2 * ncols_p * tr + 64 * 17) * sizeof(double);
 }
 
 // Returns hipErrorNotSupported (without launching) when this kernel cannot
@@ -383,42 +493,43 @@ hipError_t launch_pass16(const PassArgs<double>& pa, int64_t m, hipStream_t st,
   const int s = pa.s;
   if (pa.sp != 16 || s % 4 != 0) return hipErrorNotSupported;
   if (pa.groups != 1) return hipErrorNotSupported;
-  const int K1 = pa.upd1 ? pa.u1_c0 : 0;
-  const int K2 = pa.upd2 ? pa.u2_c0 : 0;
-  const int shared_cols = pa.upd1 ? K1 : K2;
-  // shapes in order of preference: (waves, tile rows, workgroups per CU)
-  const int shapes[5][3] = {{4, 64, 2}, {4, 32, 2}, {4, 16, 2},
-                            {8, 32, 1}, {8, 16, 1}};
-  int nw = 0, tr = 0, per_cu = 1;
-  for (const auto& sh : shapes) {
-    const int kg = sh[0] / (sh[1] / 16);
-    const int per = ((shared_cols / 4) + kg - 1) / kg;
-    if (per > kMaxKF) continue;
-    if (pa.gram && (pa.ga_p / 16 + sh[0] - 1) / sh[0] > 5) continue;
-    if (pass16_lds_bytes(pa.ncols_p, sh[1], sh[0]) * sh[2] > 160 * 1024)
-      continue;
-    nw = sh[0]; tr = sh[1]; per_cu = sh[2];
-    break;
+  if (pa.upd1 && pa.upd2 && pa.u2_c0 != pa.u1_c0 + s)
+    return hipErrorNotSupported;
+  auto al16 = [](const void* p) {
+    return (reinterpret_cast<uintptr_t>(p) & 15) == 0;
+  };
+  const bool dma = (pa.ldq % 2 == 0) && al16(pa.q) &&
+                   (!pa.fcols || (pa.ldf % 2 == 0 && al16(pa.f))) &&
+                   (!pa.ecols || (pa.lde % 2 == 0 && al16(pa.e)));
+  if (!dma) return hipErrorNotSupported;
+  const int nks1 = pa.upd1 ? (pa.u1_c0 + s) / 4 : 0;
+  const int nks2 = pa.upd2 ? pa.u2_c0 / 4 : 0;
+  const int shared = std::max(nks1, nks2);
+  const int ntb = pa.gram ? pa.gbn_p / 16 : 1;
+  if (ntb > 2) return hipErrorNotSupported;
+  const int npairs = pa.gram ? (pa.ga_p / 16) * ntb : 0;
+  const int maxp = (npairs + kNW - 1) / kNW;
+  if (maxp > 10) return hipErrorNotSupported;
+  int pick = -1;
+  if (const char* env = getenv("BCGS_PASS16_SHAPE")) {
+    const int f = atoi(env);
+    if (f >= 0 && f < kNShapes &&
+        shape_fits(kShapes[f], pa.ncols_p, shared, maxp))
+      pick = f;
   }
-  if (!nw) return hipErrorNotSupported;
-  const int ntb = pa.gbn_p / 16;
-  const int maxa = pa.gram ? (pa.ga_p / 16 + nw - 1) / nw : 0;
-  if (pa.gram && (ntb > 2 || maxa > 5)) return hipErrorNotSupported;
+  for (int i = 0; pick < 0 && i < kNShapes; ++i)
+    if (shape_fits(kShapes[i], pa.ncols_p, shared, maxp)) pick = i;
+  if (pick < 0) return hipErrorNotSupported;
+  const Shape sh = kShapes[pick];
   Args a{};
   // rows split over 256 * per_cu workgroups (256 CUs on MI355X)
-  const int64_t rpw = round_up64(cdiv(m, 256 * per_cu), 64);
+  const int64_t rpw = round_up64(cdiv(m, 256 * sh.per_cu), 64);
   const int G = (int)cdiv(m, rpw);
   a.m = pa.m; a.s = s; a.ncols = pa.ncols; a.ncols_p = pa.ncols_p;
   a.rows_per_wg = rpw;
   a.q = pa.q; a.ldq = pa.ldq; a.nq = pa.nq;
   a.f = pa.f; a.ldf = pa.ldf; a.fcols = pa.fcols;
   a.e = pa.e; a.lde = pa.lde; a.ecols = pa.ecols;
-  auto al16 = [](const void* p) {
-    return (reinterpret_cast<uintptr_t>(p) & 15) == 0;
-  };
-  a.dma = (pa.ldq % 2 == 0) && al16(pa.q) &&
-          (!pa.fcols || (pa.ldf % 2 == 0 && al16(pa.f))) &&
-          (!pa.ecols || (pa.lde % 2 == 0 && al16(pa.e)));
   a.upd1 = pa.upd1; a.u1_c0 = pa.u1_c0; a.c1 = pa.c1;
   a.dst1 = pa.dst1; a.ldd1 = pa.ldd1;
   a.upd2 = pa.upd2; a.u2_c0 = pa.u2_c0;
@@ -427,28 +538,15 @@ hipError_t launch_pass16(const PassArgs<double>& pa, int64_t m, hipStream_t st,
   a.skip_a0 = pa.skip_a0; a.skip_b1 = pa.skip_b1;
   a.partial = pa.partial;
   *G_out = G;
-  const size_t lds = pass16_lds_bytes(pa.ncols_p, tr, nw);
-  if (!pa.gram) {
-    if (nw == 4 && tr == 64) return go<4, 64, 1, false, 1>(a, G, lds, st, tag);
-    if (nw == 4 && tr == 32) return go<4, 32, 1, false, 1>(a, G, lds, st, tag);
-    if (nw == 4) return go<4, 16, 1, false, 1>(a, G, lds, st, tag);
-    if (tr == 32) return go<8, 32, 1, false, 1>(a, G, lds, st, tag);
-    return go<8, 16, 1, false, 1>(a, G, lds, st, tag);
+  const bool gram = pa.gram;
+  switch (pick) {
+    case 0: return go_shape<64, 2, 64, 2>(a, G, gram, ntb, maxp, st, tag);
+    case 1: return go_shape<32, 2, 128, 2>(a, G, gram, ntb, maxp, st, tag);
+    case 2: return go_shape<16, 2, 272, 2>(a, G, gram, ntb, maxp, st, tag);
+    case 3: return go_shape<16, 4, 272, 1>(a, G, gram, ntb, maxp, st, tag);
+    case 4: return go_shape<64, 4, 64, 1>(a, G, gram, ntb, maxp, st, tag);
+    case 5: return go_shape<32, 4, 128, 1>(a, G, gram, ntb, maxp, st, tag);
   }
-#define P16(NW_, TR_, MA_, NTB_)                                          \
-  if (nw == NW_ && tr == TR_ && ntb == NTB_ && maxa <= MA_)               \
-    return go<NW_, TR_, MA_, true, NTB_>(a, G, lds, st, tag);
-  P16(4, 64, 2, 1) P16(4, 64, 3, 1) P16(4, 64, 5, 1)
-  P16(4, 64, 2, 2) P16(4, 64, 3, 2) P16(4, 64, 5, 2)
-  P16(4, 32, 2, 1) P16(4, 32, 3, 1) P16(4, 32, 5, 1)
-  P16(4, 32, 2, 2) P16(4, 32, 3, 2) P16(4, 32, 5, 2)
-  P16(4, 16, 2, 1) P16(4, 16, 3, 1) P16(4, 16, 5, 1)
-  P16(4, 16, 2, 2) P16(4, 16, 3, 2) P16(4, 16, 5, 2)
-  P16(8, 32, 2, 1) P16(8, 32, 3, 1) P16(8, 32, 5, 1)
-  P16(8, 32, 2, 2) P16(8, 32, 3, 2) P16(8, 32, 5, 2)
-  P16(8, 16, 2, 1) P16(8, 16, 3, 1) P16(8, 16, 5, 1)
-  P16(8, 16, 2, 2) P16(8, 16, 3, 2) P16(8, 16, 5, 2)
-#undef P16
   return hipErrorNotSupported;
 }
 

@@ -349,11 +349,22 @@ __global__ __launch_bounds__(kT) void apply_kernel(
 
 }  // namespace tq
 
+int wave_tsqr_rows(int s);
+
+template <typename T>
+hipError_t launch_wave_tsqr(const TsqrPlan& tp, const T* v, int64_t ldv,
+                            T* dst, int64_t ldd, int64_t m, double* ws,
+                            double* r_out, int64_t r_rs, int64_t r_cs,
+                            hipStream_t st);
+
+// s <= 16: one wave per chunk (tsqr_wave.hip); wider blocks: one workgroup
+// per chunk (this file)
 TsqrPlan make_tsqr_plan(int64_t m, int s) {
   TsqrPlan p{};
   p.s = s;
   const int nseg = kThreads / s;
-  p.cr = tq::kRows * nseg;
+  p.wave = s <= 16;
+  p.cr = p.wave ? wave_tsqr_rows(s) : tq::kRows * nseg;
   p.fan = p.cr / s;
   if (p.fan < 2) p.fan = 2;
   p.nchunks = cdiv(m, p.cr);
@@ -374,6 +385,21 @@ TsqrPlan make_tsqr_plan(int64_t m, int s) {
   }
   p.total = off;
   return p;
+}
+
+// downward pass of the tree: coefficient blocks from the root to the leaves
+void tsqr_down(const TsqrPlan& tp, double* ws, hipStream_t st) {
+  const int s = tp.s, fan = tp.fan;
+  const double ss = (double)s * s;
+  for (int l = tp.levels; l >= 1; --l) {
+    const double n = (double)tp.nodes[l - 1];
+    prof_begin(BCGS_KERNEL_TSQR_DOWN, l, 8.0 * n * ss * 2, 2.0 * n * ss * s);
+    hipLaunchKernelGGL(tq::down_kernel, dim3((unsigned)tp.nodes[l - 1]),
+                       dim3(kThreads), 0, st, ws + tp.q_off[l],
+                       ws + tp.c_off[l], tp.nodes[l - 1], fan, s,
+                       ws + tp.c_off[l - 1], l == tp.levels ? 1 : 0);
+    prof_end();
+  }
 }
 
 template <typename T, int S>
@@ -401,15 +427,7 @@ static hipError_t launch_tsqr_s(const TsqrPlan& tp, const T* v, int64_t ldv,
                        r_cs);
     prof_end();
   }
-  for (int l = tp.levels; l >= 1; --l) {
-    const double n = (double)tp.nodes[l - 1];
-    prof_begin(BCGS_KERNEL_TSQR_DOWN, l, 8.0 * n * ss * 2, 2.0 * n * ss * s);
-    hipLaunchKernelGGL(tq::down_kernel, dim3((unsigned)tp.nodes[l - 1]),
-                       dim3(kThreads), 0, st, ws + tp.q_off[l],
-                       ws + tp.c_off[l], tp.nodes[l - 1], fan, s,
-                       ws + tp.c_off[l - 1], l == tp.levels ? 1 : 0);
-    prof_end();
-  }
+  tsqr_down(tp, ws, st);
   prof_begin(BCGS_KERNEL_TSQR_APPLY, 0, 2.0 * esz * m * s, 2.0 * m * ss);
   hipLaunchKernelGGL((tq::apply_kernel<T, S>), dim3((unsigned)tp.nchunks),
                      dim3(kThreads), lds, st, v, ldv, m, s,
@@ -422,6 +440,9 @@ template <typename T>
 hipError_t launch_tsqr(const TsqrPlan& tp, const T* v, int64_t ldv, T* dst,
                        int64_t ldd, int64_t m, double* ws, double* r_out,
                        int64_t r_rs, int64_t r_cs, hipStream_t st) {
+  if (tp.wave)
+    return launch_wave_tsqr<T>(tp, v, ldv, dst, ldd, m, ws, r_out, r_rs, r_cs,
+                               st);
   switch (tp.s) {
 #define TQ(S_) case S_: return launch_tsqr_s<T, S_>(tp, v, ldv, dst, ldd, m, \
                                                     ws, r_out, r_rs, r_cs, st);
