@@ -104,10 +104,17 @@ def aggregate(recs, steps):
 
 def kernel_name(kind, tag):
     if kind == "pass" and tag >= 10000000:
-        nw, tr = (tag // 1000000) % 10, (tag // 1000) % 1000
-        maxt, ntb = (tag // 10) % 100, tag % 10
+        # tag 1BTTTPPN: B tile buffers (+4: one workgroup per CU), TTT tile
+        # rows, PP Gram pairs per wave, N B blocks (0: no Gram)
+        b, tr = (tag // 1000000) % 10, (tag // 1000) % 1000
+        maxp, ntb = (tag // 10) % 100, tag % 10
+        deep = b > 4
+        nbuf = b - 4 if deep else b
+        cap = {64: 64, 32: 128, 16: 272}.get(tr, 0)
         gram = "true" if ntb else "false"
-        return f"pass16_kernel<{nw},{tr},{maxt},{gram},{max(ntb, 1)}>"
+        name = "pass16_deep_kernel" if deep else "pass16_kernel"
+        return (f"{name}<{tr}, {nbuf}, {cap}, {maxp}, {gram}, "
+                f"{max(ntb, 1)}>")
     if kind == "pass":
         gram, ntb, maxa = tag // 100, (tag // 10) % 10, tag % 10
         return (f"pass_kernel<double,{'true' if gram else 'false'},{ntb},"
@@ -142,6 +149,25 @@ def measured_traffic(kernel):
         if len(parts) == 5 and parts[0].replace(" ", "") == want:
             return float(parts[4]) * 1e9
     return None
+
+
+def by_name(agg):
+    """Per-step totals of every kernel, merged by name, slowest first."""
+    out = {}
+    for a in agg:
+        k = kernel_name(a["kind"], a["tag"])
+        o = out.setdefault(k, {"name": k, "launches": 0.0, "ms": 0.0,
+                               "gb": 0.0, "gflop": 0.0})
+        o["launches"] += a["n"]
+        o["ms"] += a["ms"]
+        o["gb"] += a["bytes"] / 1e9
+        o["gflop"] += a["flops"] / 1e9
+    rows = sorted(out.values(), key=lambda o: -o["ms"])
+    for o in rows:
+        o["ms"] = round(o["ms"], 4)
+        o["gb"] = round(o["gb"], 3)
+        o["gflop"] = round(o["gflop"], 2)
+    return rows
 
 
 def roofline(dom):
@@ -255,11 +281,7 @@ def main():
                "gbs": round(model_bytes / (ms * 1e-3) / 1e9, 1),
                "tflops": round(model_flops / (ms * 1e-3) / 1e12, 2),
                "status": info.status, "syncs": info.syncs,
-               "kernels": [{"name": kernel_name(a["kind"], a["tag"]),
-                            "launches": a["n"], "ms": round(a["ms"], 4),
-                            "gb": round(a["bytes"] / 1e9, 3),
-                            "gflop": round(a["flops"] / 1e9, 2)}
-                           for a in agg[:8]],
+               "kernels": by_name(agg),
                "_agg": agg}
         if not args.no_check:
             loo, resid = accuracy(X, Q, R)

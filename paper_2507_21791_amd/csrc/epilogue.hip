@@ -71,6 +71,84 @@ __device__ void chol_lds(EpiSmem& sm, int s, bcgs_info* info, int block,
   __syncthreads();
 }
 
+__device__ __forceinline__ double lane_bcast(double v, int lane) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+  return __hiloint2double(hi, lo);
+}
+
+// The same factorization by wave 0 alone for a compile-time s <= 16: lane
+// l holds column l in registers, the pivot and the row of R are broadcast
+// with readlane, so no step needs a barrier.  Same breakdown rule, same
+// record in bcgs_info, same NaN fill.
+template <int S>
+__device__ void chol_wave(EpiSmem& sm, bcgs_info* info, int block,
+                          int stage) {
+  if (threadIdx.x < 64) {
+    const int l = threadIdx.x;
+    double col[S];
+#pragma unroll
+    for (int i = 0; i < S; ++i) col[i] = l < S ? sm.A[i * S + l] : 0.0;
+    bool bad = false;
+#pragma unroll
+    for (int j = 0; j < S; ++j) {
+      const double d = lane_bcast(col[j], j);
+      if (!(isfinite(d) && d > 0.0) && !bad) {
+        if (l == 0 && info->status == BCGS_OK) {
+          info->status = BCGS_ERR_BREAKDOWN;
+          info->block = block;
+          info->pivot = j;
+          info->stage = stage;
+          info->value = d;
+        }
+        bad = true;
+      }
+      const double r = sqrt(d);
+      const double rj = l > j ? col[j] / r : (l == j ? r : col[j]);
+      col[j] = rj;                         // R(j, l)
+#pragma unroll
+      for (int i = j + 1; i < S; ++i) {
+        const double rji = lane_bcast(rj, i);   // R(j, i)
+        if (l >= i) col[i] -= rji * rj;
+      }
+    }
+    if (l < S) {
+#pragma unroll
+      for (int i = 0; i < S; ++i)
+        sm.A[i * S + l] = bad ? NAN : (i <= l ? col[i] : 0.0);
+    }
+  }
+  __syncthreads();
+}
+
+template <int S>
+__device__ __forceinline__ void chol(EpiSmem& sm, int s, bcgs_info* info,
+                                     int block, int stage) {
+  if constexpr (S > 0 && S <= 16) chol_wave<S>(sm, info, block, stage);
+  else chol_lds(sm, s, info, block, stage);
+}
+
+// T^{-1} of the upper triangular s x s matrix T (row-major, LDS) into Ti:
+// lane j of wave 0 forms column j by back substitution in registers.
+template <int S>
+__device__ void tri_inv_wave(const double* T, double* Ti) {
+  if (threadIdx.x < 64) {
+    const int j = threadIdx.x;
+    double x[S];
+#pragma unroll
+    for (int i = S - 1; i >= 0; --i) {
+      double v = i == j ? 1.0 : 0.0;
+#pragma unroll
+      for (int k = i + 1; k < S; ++k) v -= T[i * S + k] * x[k];
+      x[i] = i <= j ? v / T[i * S + i] : 0.0;
+    }
+    if (j < S) {
+#pragma unroll
+      for (int i = 0; i < S; ++i) Ti[i * S + j] = x[i];
+    }
+  }
+}
+
 __device__ __forceinline__ double gram_at(const EpiArgs& a, int r, int c) {
   return a.gram[(size_t)c * a.gld + r];
 }
@@ -100,11 +178,18 @@ __device__ void assemble_r(EpiSmem& sm, const EpiArgs& a, const double* c1,
     double y[S ? S : kMaxS];
 #pragma unroll
     for (int k = 0; k < s; ++k) y[k] = c1[(size_t)i * sp + k];
-#pragma unroll
+    // column loop kept rolled: the T2 column is re-read from LDS per
+    // column instead of the whole matrix being held in registers
+#pragma unroll 1
     for (int c = 0; c < s; ++c) {
       double acc = c2[(size_t)i * sp + c];
+      if constexpr (S > 0) {
 #pragma unroll
-      for (int k = 0; k <= c; ++k) acc += y[k] * T2[k * s + c];
+        for (int k = 0; k < S; ++k)
+          if (k <= c) acc += y[k] * T2[k * S + c];
+      } else {
+        for (int k = 0; k <= c; ++k) acc += y[k] * T2[k * s + c];
+      }
       a.r[(size_t)(js + c) * a.ldr + i] = acc;
     }
   }
@@ -130,7 +215,9 @@ __device__ void make_coef(EpiSmem& sm, double* F, const double* C, int K,
     for (int e = tid; e < s * s; e += kThreads)
       Tl[e] = T[(e / s) * sp + e % s];
     __syncthreads();
-    if (tid < s) {
+    if constexpr (S > 0 && S <= 16) {
+      tri_inv_wave<S>(Tl, Ti);
+    } else if (tid < s) {
       const int j = tid;
       for (int i = s - 1; i >= 0; --i) {
         double x = 0.0;
@@ -153,12 +240,17 @@ __device__ void make_coef(EpiSmem& sm, double* F, const double* C, int K,
 #pragma unroll
     for (int k = 0; k < s; ++k) cr[k] = C[(size_t)i * sp + k];
     double* fr = F + (size_t)i * sp;
-#pragma unroll
-    for (int c = 0; c < (S ? (S + 15) / 16 * 16 : sp); ++c) {
+#pragma unroll 1
+    for (int c = 0; c < sp; ++c) {
       double v = 0.0;
       if (c < s) {
-        if (scaled) {
+        if constexpr (S > 0) {
 #pragma unroll
+          for (int k = 0; k < S; ++k) {
+            if (scaled && k <= c) v -= cr[k] * Ti[k * S + c];
+            if (!scaled && k == c) v = -cr[k];
+          }
+        } else if (scaled) {
           for (int k = 0; k <= c; ++k) v -= cr[k] * Ti[k * s + c];
         } else {
           v = -cr[c];
@@ -192,11 +284,15 @@ __device__ void fold_coefs(EpiSmem& sm, const EpiArgs& a) {
 #pragma unroll
     for (int k = 0; k < s; ++k) fr[k] = a.f1[(size_t)i * sp + k];
     double* out = a.f2 + (size_t)i * sp;
-#pragma unroll
+#pragma unroll 1
     for (int c = 0; c < s; ++c) {
       double v = i < K1 ? out[c] : 0.0;
+      if constexpr (S > 0) {
 #pragma unroll
-      for (int k = 0; k < s; ++k) v += fr[k] * M[k * s + c];
+        for (int k = 0; k < S; ++k) v += fr[k] * M[k * S + c];
+      } else {
+        for (int k = 0; k < s; ++k) v += fr[k] * M[k * s + c];
+      }
       out[c] = v;
     }
   }
@@ -260,7 +356,7 @@ __device__ void epilogue_body(EpiArgs a, EpiSmem& sm) {
       sm.A[e] = acc;
     }
     __syncthreads();
-    chol_lds(sm, s, a.info, 1, 0);
+    chol<S>(sm, s, a.info, 1, 0);
     store_tri(a.t2, sp, s, sm.A);
     return;
   }
@@ -313,7 +409,7 @@ __device__ void epilogue_body(EpiArgs a, EpiSmem& sm) {
     if (e < s * s) sm.A[e] = gram_at(a, js + e / s, e % s) - yy[t];
   }
   __syncthreads();
-  chol_lds(sm, s, a.info, a.j, 1);
+  chol<S>(sm, s, a.info, a.j, 1);
   // 2. R block column j with the current S (C2, T2) and the new Y, Y_jj
   //    (C1/T1 are overwritten below, so write the new Y into C1 first)
   for (int e = tid; e < js * sp; e += kThreads) {
@@ -332,7 +428,21 @@ __device__ void epilogue_body(EpiArgs a, EpiSmem& sm) {
     if (e < s * s) sm.B[e] = gram_at(a, js + e / s, s + e % s) - yz[t];
   }
   __syncthreads();
-  if (tid < s) {
+  if constexpr (S > 0 && S <= 16) {
+    if (tid < S) {
+      const int c = tid;
+      double x[S];
+#pragma unroll
+      for (int i = 0; i < S; ++i) {
+        double acc = sm.B[i * S + c];
+#pragma unroll
+        for (int k = 0; k < i; ++k) acc -= sm.A[k * S + i] * x[k];
+        x[i] = acc / sm.A[i * S + i];
+      }
+#pragma unroll
+      for (int i = 0; i < S; ++i) sm.B[i * S + c] = x[i];
+    }
+  } else if (tid < s) {
     const int c = tid;
     for (int i = 0; i < s; ++i) {
       double acc = sm.B[i * s + c];
@@ -368,7 +478,7 @@ __device__ void epilogue_body(EpiArgs a, EpiSmem& sm) {
     if (e < s * s) sm.A[e] = tmp[t];
   }
   __syncthreads();
-  chol_lds(sm, s, a.info, a.j + 1, 0);
+  chol<S>(sm, s, a.info, a.j + 1, 0);
   store_tri(a.t2, sp, s, sm.A);
 }
 
