@@ -103,17 +103,19 @@ def aggregate(recs, steps):
 
 
 def kernel_name(kind, tag):
-    if kind == "pass" and tag >= 10000000:
-        # tag 1BTTTPPN: B tile buffers (+4: one workgroup per CU), TTT tile
-        # rows, PP Gram pairs per wave, N B blocks (0: no Gram)
-        b, tr = (tag // 1000000) % 10, (tag // 1000) % 1000
-        maxp, ntb = (tag // 10) % 100, tag % 10
-        deep = b > 4
-        nbuf = b - 4 if deep else b
+    if kind == "pass" and tag >= 1000000000:
+        # tag 1WPBSTTPPN: waves, workgroups per CU, tile buffers, both
+        # partial-sum areas, tile rows, Gram pairs per wave, B blocks
+        nw, pc = (tag // 100000000) % 10, (tag // 10000000) % 10
+        nbuf, scr2 = (tag // 1000000) % 10, (tag // 100000) % 10
+        tr, maxp, ntb = (tag // 1000) % 100, (tag // 10) % 100, tag % 10
         cap = {64: 64, 32: 128, 16: 272}.get(tr, 0)
         gram = "true" if ntb else "false"
-        name = "pass16_deep_kernel" if deep else "pass16_kernel"
-        return (f"{name}<{tr}, {nbuf}, {cap}, {maxp}, {gram}, "
+        if pc == 2:
+            return (f"pass16_kernel<{tr}, {nbuf}, {cap}, {maxp}, {gram}, "
+                    f"{max(ntb, 1)}>")
+        return (f"pass16_deep_kernel<{tr}, {nbuf}, {cap}, {nw}, "
+                f"{'true' if scr2 else 'false'}, {maxp}, {gram}, "
                 f"{max(ntb, 1)}>")
     if kind == "pass":
         gram, ntb, maxa = tag // 100, (tag // 10) % 10, tag % 10

@@ -483,7 +483,7 @@ __device__ void epilogue_body(EpiArgs a, EpiSmem& sm) {
 }
 
 hipError_t launch_epilogue(const EpiArgs& a, hipStream_t st) {
-  prof_begin(BCGS_KERNEL_EPILOGUE, a.mode, 0.0, 0.0);
+  prof_begin(BCGS_KERNEL_EPILOGUE, a.mode * 1000 + a.j, 0.0, 0.0);
   switch (a.s) {
 #define EPI(S_) case S_: hipLaunchKernelGGL(epilogue_kernel<S_>, dim3(1), \
                                             dim3(kThreads), 0, st, a); break;

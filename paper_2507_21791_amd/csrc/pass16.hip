@@ -17,6 +17,10 @@
 //    per-column key, which keeps both MFMA fragment patterns (16 columns x
 //    4 rows for the Gram, 4 columns x 16 rows for the updates) free of bank
 //    conflicts.
+//  * The Gram uses the FP64 4x4x4 MFMA (four 4x4 blocks per instruction),
+//    which gfx950 runs at about 1.5x the rate of the 16x16x4 form (a 16x16
+//    output tile is four such instructions); the block updates use the
+//    16x16x4 form, whose operands cost a quarter of the LDS reads.
 //  * Block updates B <- [Q B] F (F = [-C T^{-1}; T^{-1}], see common.h):
 //    waves = (TR/16 row blocks) x (KG K-ranges); every wave keeps its slice
 //    of the coefficient fragments in registers for the whole kernel.  When
@@ -39,13 +43,22 @@ namespace bcgs {
 
 namespace p16 {
 
-typedef double v4d __attribute__((ext_vector_type(4)));
 constexpr int kMaxKF = 16;            // C fragments per update per wave
-constexpr int kNW = 4;                // waves per workgroup
-constexpr int kT = kNW * 64;
 
-__device__ __forceinline__ v4d mfma(double a, double b, v4d c) {
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+// v_mfma_f64_16x16x4f64: A[l % 16][l / 16], B[l / 16][l % 16],
+// D[l / 16 + 4 v][l % 16]
+__device__ __forceinline__ v4d mfma16(double a, double b, v4d c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// v_mfma_f64_4x4x4f64: four independent 4x4x4 products per wave.  With
+// lane l = i + 4 b + 16 k (operand A), l = j + 4 b + 16 k (operand B) and
+// l = j + 4 b + 16 i (result), block b computes D_b = A_b B_b + C_b.  On
+// gfx950 this form sustains about 1.5x the FP64 rate of the 16x16x4 one.
+__device__ __forceinline__ double mfma4(double a, double b, double c) {
+  return __builtin_amdgcn_mfma_f64_4x4x4f64(a, b, c, 0, 0, 0);
 }
 
 // swizzle key of column c: a permutation of the granule index
@@ -110,9 +123,9 @@ __device__ __forceinline__ const double* col_ptr(const Args& a, int c,
 }
 
 // Synchronous staging of a short last tile: zero past the row count.
-template <int TR>
+template <int TR, int NW>
 __device__ void tile_sync(const Args& a, double* buf, int64_t r0, int rows) {
-  for (int idx = threadIdx.x; idx < a.ncols * TR; idx += kT) {
+  for (int idx = threadIdx.x; idx < a.ncols * TR; idx += NW * 64) {
     const int c = idx / TR, r = idx % TR;
     double v = 0.0;
     if (r < rows) {
@@ -126,12 +139,12 @@ __device__ void tile_sync(const Args& a, double* buf, int64_t r0, int rows) {
 
 // Sum the K-range partial products of one block update (scr: [KG][TR][17])
 // into the tile columns [uc0, uc0 + s) and into dst (rows < rows).
-template <int TR, int KG>
+template <int TR, int KG, int NW>
 __device__ __forceinline__ void combine(const Args& a, double* tile,
                                         const double* scr, int uc0,
                                         double* dst, int64_t ldd, int64_t r0,
                                         int rows) {
-  for (int t = threadIdx.x; t < TR * 16; t += kT) {
+  for (int t = threadIdx.x; t < TR * 16; t += NW * 64) {
     const int r = t % TR, c = t / TR;
     if (c >= a.s) continue;
     double part[KG];
@@ -146,9 +159,9 @@ __device__ __forceinline__ void combine(const Args& a, double* tile,
 }
 
 // One workgroup per row range.  TR tile rows; NBUF tile buffers of CAP
-// columns, each its own LDS object; PC workgroups per CU; MAXP Gram pairs
-// per wave; NTB B blocks.  With one workgroup per CU there is LDS room for
-// both updates' partial sums.
+// columns, each its own LDS object; PC workgroups per CU; NW waves; SCR2:
+// LDS room for both updates' partial sums; MAXP Gram pairs per wave; NTB
+// B blocks.
 //
 // Copy pipeline.  Each wave issues exactly IPW copy instructions per tile
 // (waves with fewer instructions repeat their last one, lanes past the last
@@ -158,14 +171,14 @@ __device__ __forceinline__ void combine(const Args& a, double* tile,
 // flight.  The tile loop is unrolled by NBUF so that every LDS access names
 // its buffer statically; the compiler then sees that the copies in flight
 // target other buffers and inserts no waits of its own.
-template <int TR, int NBUF, int CAP, int PC, int MAXP, bool GRAM, int NTB>
+template <int TR, int NBUF, int CAP, int PC, int NW, bool SCR2, int MAXP,
+          bool GRAM, int NTB>
 struct Kernel {
-  static constexpr bool SCR2 = PC == 1;
   static constexpr int MB = TR / 16;          // row blocks per tile
-  static constexpr int KG = kNW / MB;         // K ranges per update
+  static constexpr int KG = NW / MB;          // K ranges per update
   static constexpr int kTail = (4 + KG - 1) / KG;
   static constexpr int CPI = 1024 / (TR * 8); // columns per copy instruction
-  static constexpr int IPW = ((CAP + CPI - 1) / CPI + kNW - 1) / kNW;
+  static constexpr int IPW = ((CAP + CPI - 1) / CPI + NW - 1) / NW;
   static constexpr int TE = CAP * TR;         // doubles per buffer
   static_assert(CAP % CPI == 0, "buffer holds whole copy instructions");
 
@@ -175,7 +188,7 @@ struct Kernel {
     double c2o[kTail];                 // update 2, steps over its own block
     int kb, ke, nks2, sq;
     int mb, kg;
-    v4d acc[MAXP];
+    double acc[MAXP][4];
     int npairs;
   };
 
@@ -188,7 +201,7 @@ struct Kernel {
     const int ninst = (a.ncols + CPI - 1) / CPI;
 #pragma unroll
     for (int i = 0; i < IPW; ++i) {
-      const int ins = min(wave + kNW * i, ninst - 1);
+      const int ins = min(wave + NW * i, ninst - 1);
       const int c = ins * CPI + lane / kGran;
       const int g = lane % kGran;
       int64_t ld;
@@ -199,98 +212,125 @@ struct Kernel {
     }
   }
 
+  // block updates of one tile (U1: update 1, U2: update 2 present), with
+  // the 16x16x4 MFMA: the update reads one tile fragment per K-step and
+  // shares it between both updates, which keeps its LDS traffic at a
+  // quarter of what the 4x4x4 form would need
+  template <bool U1, bool U2>
+  static __device__ __forceinline__ void updates(const Args& a, State& S,
+                                                 double* tile, double* scr,
+                                                 int64_t r0, int rows) {
+    const int lane = threadIdx.x & 63;
+    const int li = lane & 15, lk = lane >> 4;
+    // K-steps in uniform chunks of 4; inside a chunk the four fragment
+    // loads are issued first; K-steps past ke read a valid address and
+    // meet zero coefficient fragments, so no lane-divergent branches
+    v4d acc1 = {0.0, 0.0, 0.0, 0.0}, acc2 = {0.0, 0.0, 0.0, 0.0};
+    v4d acc1b = {0.0, 0.0, 0.0, 0.0}, acc2b = {0.0, 0.0, 0.0, 0.0};
+    const int kcl = max(S.kb, S.ke - 1);
+    const int row = S.mb * 16 + li;
+#pragma unroll
+    for (int q = 0; q < kMaxKF / 4; ++q) {
+      if (4 * q >= S.ke - S.kb) break;
+      double av[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int k = min(S.kb + 4 * q + u, kcl);
+        av[u] = tile[at<TR>(4 * k + lk, row)];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; u += 2) {
+        if (U1) acc1 = mfma16(av[u], S.c1f[4 * q + u], acc1);
+        if (U2) acc2 = mfma16(av[u], S.c2f[4 * q + u], acc2);
+        if (U1) acc1b = mfma16(av[u + 1], S.c1f[4 * q + u + 1], acc1b);
+        if (U2) acc2b = mfma16(av[u + 1], S.c2f[4 * q + u + 1], acc2b);
+      }
+    }
+    if (U2) {
+#pragma unroll
+      for (int u = 0; u < kTail; ++u) {
+        const int t = S.kg + KG * u;
+        if (t < S.sq)
+          acc2b = mfma16(tile[at<TR>(4 * (S.nks2 + t) + lk, row)], S.c2o[u],
+                         acc2b);
+      }
+    }
+    acc1 += acc1b;
+    acc2 += acc2b;
+    // partial sums: scr[kg][row][col], row stride 17; result v at lane l is
+    // row mb*16 + lk + 4 v, column li
+    double* scr1 = scr;
+    double* scr2 = SCR2 ? scr + KG * TR * 17 : scr;
+    const int wbase = (S.kg * TR + S.mb * 16 + lk) * 17 + li;
+    if (U1) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) scr1[wbase + 4 * v * 17] = acc1[v];
+    }
+    if (U2 && (SCR2 || !U1)) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) scr2[wbase + 4 * v * 17] = acc2[v];
+    }
+    lds_barrier();
+    if (U1) combine<TR, KG, NW>(a, tile, scr1, a.u1_c0, a.dst1, a.ldd1, r0, rows);
+    if (U2 && (SCR2 || !U1))
+      combine<TR, KG, NW>(a, tile, scr2, a.u2_c0, a.dst2, a.ldd2, r0, rows);
+    lds_barrier();
+    if (!SCR2 && U1 && U2) {
+      // one partial-sum area: the second update's round
+#pragma unroll
+      for (int v = 0; v < 4; ++v) scr[wbase + 4 * v * 17] = acc2[v];
+      lds_barrier();
+      combine<TR, KG, NW>(a, tile, scr, a.u2_c0, a.dst2, a.ldd2, r0, rows);
+      lds_barrier();
+    }
+  }
+
   static __device__ __forceinline__ void process(const Args& a, State& S,
                                                  double* tile, double* scr,
                                                  int64_t r0, int rows) {
     const int lane = threadIdx.x & 63;
     const int li = lane & 15, lk = lane >> 4;
-    // ---- block updates ----
-    if (a.upd1 || a.upd2) {
-      // K-steps in uniform chunks of 4; inside a chunk the four fragment
-      // loads are issued first; K-steps past ke read a valid address and
-      // meet zero coefficient fragments, so no lane-divergent branches
-      v4d acc1 = {0.0, 0.0, 0.0, 0.0}, acc2 = {0.0, 0.0, 0.0, 0.0};
-      v4d acc1b = {0.0, 0.0, 0.0, 0.0}, acc2b = {0.0, 0.0, 0.0, 0.0};
-      const int kcl = max(S.kb, S.ke - 1);
-      const int row = S.mb * 16 + li;
-#pragma unroll
-      for (int q = 0; q < kMaxKF / 4; ++q) {
-        if (4 * q >= S.ke - S.kb) break;
-        double av[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const int k = min(S.kb + 4 * q + u, kcl);
-          av[u] = tile[at<TR>(4 * k + lk, row)];
-        }
-#pragma unroll
-        for (int u = 0; u < 4; u += 2) {
-          if (a.upd1) acc1 = mfma(av[u], S.c1f[4 * q + u], acc1);
-          if (a.upd2) acc2 = mfma(av[u], S.c2f[4 * q + u], acc2);
-          if (a.upd1) acc1b = mfma(av[u + 1], S.c1f[4 * q + u + 1], acc1b);
-          if (a.upd2) acc2b = mfma(av[u + 1], S.c2f[4 * q + u + 1], acc2b);
-        }
-      }
-      if (a.upd2) {
-#pragma unroll
-        for (int u = 0; u < kTail; ++u) {
-          const int t = S.kg + KG * u;
-          if (t < S.sq)
-            acc2b = mfma(tile[at<TR>(4 * (S.nks2 + t) + lk, row)], S.c2o[u],
-                         acc2b);
-        }
-      }
-      acc1 += acc1b;
-      acc2 += acc2b;
-      double* scr1 = scr;
-      double* scr2 = SCR2 ? scr + KG * TR * 17 : scr;
-      if (a.upd1) {
-#pragma unroll
-        for (int v = 0; v < 4; ++v)
-          scr1[(S.kg * TR + S.mb * 16 + lk + 4 * v) * 17 + li] = acc1[v];
-      }
-      if (a.upd2 && (SCR2 || !a.upd1)) {
-#pragma unroll
-        for (int v = 0; v < 4; ++v)
-          scr2[(S.kg * TR + S.mb * 16 + lk + 4 * v) * 17 + li] = acc2[v];
-      }
-      lds_barrier();
-      if (a.upd1)
-        combine<TR, KG>(a, tile, scr1, a.u1_c0, a.dst1, a.ldd1, r0, rows);
-      if (a.upd2 && (SCR2 || !a.upd1))
-        combine<TR, KG>(a, tile, scr2, a.u2_c0, a.dst2, a.ldd2, r0, rows);
-      lds_barrier();
-      if (!SCR2 && a.upd1 && a.upd2) {
-        // one partial-sum area: the second update's round
-#pragma unroll
-        for (int v = 0; v < 4; ++v)
-          scr[(S.kg * TR + S.mb * 16 + lk + 4 * v) * 17 + li] = acc2[v];
-        lds_barrier();
-        combine<TR, KG>(a, tile, scr, a.u2_c0, a.dst2, a.ldd2, r0, rows);
-        lds_barrier();
-      }
-    }
-    // ---- Gram: two MFMA K-steps per 16-byte LDS load (lane group lk
-    //      takes rows kk + 2 lk and kk + 2 lk + 1).  Pair i of this wave is
-    //      p = wave + 4 i; since 4 is a multiple of NTB, every pair of a
-    //      wave uses the same B block, wave % NTB. ----
+    // ---- block updates, as out^T = F^T tile^T in 4x4x4 blocks: the A
+    //      operand is the F fragment (F[4k + lk][li], kept in registers),
+    //      the B operand of instruction q holds rows mb*16 + 4 j + q (j =
+    //      lane & 3) of tile column 4k + lk, so a lane's four B values are
+    //      four consecutive rows (two 16-byte loads per K-step).  Output
+    //      q at lane l: row mb*16 + 4 (l & 3) + q, column 4 ((l >> 2) & 3) +
+    //      (l >> 4). ----
+    if (a.upd1 && a.upd2) updates<true, true>(a, S, tile, scr, r0, rows);
+    else if (a.upd2) updates<false, true>(a, S, tile, scr, r0, rows);
+    else if (a.upd1) updates<true, false>(a, S, tile, scr, r0, rows);
+    // ---- Gram in 4x4x4 blocks: A operand = the pair's A block fragment
+    //      (column pa + li, the 16x16x4 layout), B operand of instruction q
+    //      = column gb + 4 (lane & 3) + q; two K-steps per 16-byte load
+    //      (lane group lk takes rows kk + 2 lk and kk + 2 lk + 1).  Pair i of
+    //      this wave is p = wave + NW i; since NW is a multiple of NTB, all
+    //      pairs of a wave share the B block wave % NTB. ----
     if (GRAM) {
       const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-      const int bcol = a.gb0 + (wave % NTB) * 16 + li;
+      const int bcol = a.gb0 + (wave % NTB) * 16 + 4 * (lane & 3);
 #pragma unroll
       for (int kk = 0; kk < TR; kk += 8) {
         const int r = kk + 2 * lk;
-        const double2 bf =
-            *reinterpret_cast<const double2*>(tile + at<TR>(bcol, r));
+        double2 bq[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          bq[q] = *reinterpret_cast<const double2*>(tile + at<TR>(bcol + q, r));
 #pragma unroll
         for (int i = 0; i < MAXP; ++i) {
-          const int p = wave + kNW * i;
+          const int p = wave + NW * i;
           if (p < S.npairs) {          // wave-uniform
             const double2 af = *reinterpret_cast<const double2*>(
                 tile + at<TR>((p / NTB) * 16 + li, r));
-            S.acc[i] = mfma(af.x, bf.x, S.acc[i]);
-            S.acc[i] = mfma(af.y, bf.y, S.acc[i]);
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+              S.acc[i][q] = mfma4(af.x, bq[q].x, S.acc[i][q]);
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+              S.acc[i][q] = mfma4(af.y, bq[q].y, S.acc[i][q]);
           }
         }
+        asm volatile("" ::: "memory");
       }
     }
   }
@@ -308,12 +348,12 @@ struct Kernel {
     process(a, S, bufs[I], scr, row0 + t * TR, TR);
   }
 
-  static __device__ void run(const Args& a) {
+  static __device__ __forceinline__ void run(const Args& a) {
     __shared__ double b0[TE];
     __shared__ double b1[TE];
     __shared__ double b2[NBUF > 2 ? TE : 1];
     __shared__ double b3[NBUF > 3 ? TE : 1];
-    __shared__ double scr[(SCR2 ? 2 : 1) * 64 * 17];
+    __shared__ double scr[(SCR2 ? 2 : 1) * KG * TR * 17];
     double* const bufs[4] = {b0, b1, b2, b3};
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform
@@ -350,17 +390,19 @@ struct Kernel {
       S.c2o[u] = (a.upd2 && t < S.sq)
                      ? a.c2[(4 * (S.nks2 + t) + lk) * 16 + li] : 0.0;
     }
-    // ---- Gram pairs p = wave + 4 i, p = (A block) * NTB + (B block) ----
+    // ---- Gram pairs p = wave + NW i, p = (A block) * NTB + (B block) ----
     const int nta = a.ga_p >> 4;
     S.npairs = GRAM ? nta * NTB : 1;
 #pragma unroll
-    for (int i = 0; i < MAXP; ++i) S.acc[i] = v4d{0.0, 0.0, 0.0, 0.0};
+    for (int i = 0; i < MAXP; ++i)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) S.acc[i][q] = 0.0;
     // the fragment loads above complete here, so no wait for them is left
     // pending inside the tile loop, where it would drain the copies
     __builtin_amdgcn_s_waitcnt(0);
     // zero the columns past the copied ones (multiplied by zero weights
     // in the updates; their Gram entries are not read)
-    for (int idx = a.ncols_p * TR + tid; idx < TE; idx += kT) {
+    for (int idx = a.ncols_p * TR + tid; idx < TE; idx += NW * 64) {
       b0[idx] = 0.0;
       b1[idx] = 0.0;
       if (NBUF > 2) b2[idx] = 0.0;
@@ -396,7 +438,7 @@ struct Kernel {
     if (rt < row_end) {
       __builtin_amdgcn_s_waitcnt(0);
       lds_barrier();
-      tile_sync<TR>(a, b0, rt, (int)(row_end - rt));
+      tile_sync<TR, NW>(a, b0, rt, (int)(row_end - rt));
       lds_barrier();
       process(a, S, b0, scr, rt, (int)(row_end - rt));
     }
@@ -405,76 +447,93 @@ struct Kernel {
       double* out = a.partial + (size_t)g * a.ga_p * a.gbn_p;
 #pragma unroll
       for (int i = 0; i < MAXP; ++i) {
-        const int p = wave + kNW * i;
+        const int p = wave + NW * i;
         if (p >= S.npairs) continue;
         const int ta = (p / NTB) * 16, b = p % NTB;
         if (ta >= a.skip_a0 && b * 16 + 16 <= a.skip_b1) continue;
+        // acc[i][q] at lane l: A column ta + 4 ((l >> 2) & 3) + lk,
+        // B column b * 16 + 4 (l & 3) + q
 #pragma unroll
-        for (int v = 0; v < 4; ++v)
-          out[(size_t)(b * 16 + li) * a.ga_p + ta + lk + 4 * v] = S.acc[i][v];
+        for (int q = 0; q < 4; ++q)
+          out[(size_t)(b * 16 + 4 * (lane & 3) + q) * a.ga_p + ta +
+              4 * ((lane >> 2) & 3) + lk] = S.acc[i][q];
       }
     }
   }
 };
 
-// two workgroups per CU: at most 256 registers per lane
+// two 4-wave workgroups per CU: at most 256 registers per lane
 template <int TR, int NBUF, int CAP, int MAXP, bool GRAM, int NTB>
-__global__ __launch_bounds__(kT) __attribute__((amdgpu_waves_per_eu(2)))
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
 void pass16_kernel(Args a) {
-  Kernel<TR, NBUF, CAP, 2, MAXP, GRAM, NTB>::run(a);
+  Kernel<TR, NBUF, CAP, 2, 4, false, MAXP, GRAM, NTB>::run(a);
 }
 
-// one workgroup per CU: the register file of the SIMD to itself
-template <int TR, int NBUF, int CAP, int MAXP, bool GRAM, int NTB>
-__global__ __launch_bounds__(kT) __attribute__((amdgpu_waves_per_eu(1)))
+// one workgroup of NW waves per CU
+template <int TR, int NBUF, int CAP, int NW, bool SCR2, int MAXP, bool GRAM,
+          int NTB>
+__global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(NW / 4)))
 void pass16_deep_kernel(Args a) {
-  Kernel<TR, NBUF, CAP, 1, MAXP, GRAM, NTB>::run(a);
+  Kernel<TR, NBUF, CAP, 1, NW, SCR2, MAXP, GRAM, NTB>::run(a);
 }
 
-template <int TR, int NBUF, int CAP, int PC, int MAXP, bool GRAM, int NTB>
+template <int TR, int NBUF, int CAP, int PC, int NW, bool SCR2, int MAXP,
+          bool GRAM, int NTB>
 static hipError_t go(const Args& a, int G, hipStream_t st, int* tag) {
-  // 1 B TT PP N: tile buffers (+4 for one workgroup per CU), tile rows,
-  // Gram pairs per wave, B blocks (0: no Gram)
-  *tag = 10000000 + (NBUF + (PC == 1 ? 4 : 0)) * 1000000 + TR * 1000 +
-         MAXP * 10 + (GRAM ? NTB : 0);
+  // 1 W P B S TT PP N: waves, workgroups per CU, tile buffers, both
+  // partial-sum areas, tile rows, Gram pairs per wave, B blocks (0: no
+  // Gram)
+  *tag = 1000000000 + NW * 100000000 + PC * 10000000 + NBUF * 1000000 +
+         (SCR2 ? 100000 : 0) + TR * 1000 + MAXP * 10 + (GRAM ? NTB : 0);
   if constexpr (PC == 2)
     hipLaunchKernelGGL((pass16_kernel<TR, NBUF, CAP, MAXP, GRAM, NTB>),
-                       dim3((unsigned)G), dim3(kT), 0, st, a);
+                       dim3((unsigned)G), dim3(256), 0, st, a);
   else
-    hipLaunchKernelGGL((pass16_deep_kernel<TR, NBUF, CAP, MAXP, GRAM, NTB>),
-                       dim3((unsigned)G), dim3(kT), 0, st, a);
+    hipLaunchKernelGGL(
+        (pass16_deep_kernel<TR, NBUF, CAP, NW, SCR2, MAXP, GRAM, NTB>),
+        dim3((unsigned)G), dim3(NW * 64), 0, st, a);
   return hipGetLastError();
 }
 
-// (tile rows, buffers, column capacity, workgroups per CU)
-struct Shape { int tr, nbuf, cap, per_cu; };
+// (tile rows, buffers, column capacity, workgroups per CU, waves, both
+// partial-sum areas)
+struct Shape { int tr, nbuf, cap, per_cu, nw, scr2; };
 
 // in order of preference; BCGS_PASS16_SHAPE=<index> forces one (tuning).
 // launch_pass16's switch instantiates the same list, entry by entry.
 constexpr Shape kShapes[] = {
-    {64, 2, 64, 2}, {32, 2, 128, 2}, {16, 2, 272, 2},
-    {16, 4, 272, 1}, {64, 4, 64, 1}, {32, 4, 128, 1}};
+    {64, 2, 64, 2, 4, 0},  {32, 2, 128, 2, 4, 0}, {16, 2, 272, 2, 4, 0},
+    {16, 4, 272, 1, 4, 1}, {16, 3, 272, 1, 8, 1}, {16, 4, 272, 1, 8, 0}};
 constexpr int kNShapes = sizeof(kShapes) / sizeof(kShapes[0]);
 
+static int shape_maxp(const Shape& sh, int npairs) {
+  return (npairs + sh.nw - 1) / sh.nw;
+}
+
 static bool shape_fits(const Shape& sh, int ncols_p, int shared_ksteps,
-                       int maxp) {
-  const int kg = kNW / (sh.tr / 16);
+                       int npairs) {
+  const int kg = sh.nw / (sh.tr / 16);
   if ((shared_ksteps + kg - 1) / kg > kMaxKF) return false;
+  if (shape_maxp(sh, npairs) > 9) return false;
   return ncols_p <= sh.cap;
 }
 
-template <int TR, int NBUF, int CAP, int PC>
+template <int TR, int NBUF, int CAP, int PC, int NW, bool SCR2>
 static hipError_t go_shape(const Args& a, int G, bool gram, int ntb,
                            int maxp, hipStream_t st, int* tag) {
-  if (!gram) return go<TR, NBUF, CAP, PC, 1, false, 1>(a, G, st, tag);
+#define GO(M_, G_, N_) go<TR, NBUF, CAP, PC, NW, SCR2, M_, G_, N_>(a, G, st, tag)
+  if (!gram) return GO(1, false, 1);
   if (ntb == 1) {
-    if (maxp <= 2) return go<TR, NBUF, CAP, PC, 2, true, 1>(a, G, st, tag);
-    if (maxp <= 5) return go<TR, NBUF, CAP, PC, 5, true, 1>(a, G, st, tag);
-    return go<TR, NBUF, CAP, PC, 10, true, 1>(a, G, st, tag);
+    if (maxp <= 2) return GO(2, true, 1);
+    if (maxp <= 5) return GO(5, true, 1);
+    if (maxp <= 7) return GO(7, true, 1);
+    return GO(9, true, 1);
   }
-  if (maxp <= 2) return go<TR, NBUF, CAP, PC, 2, true, 2>(a, G, st, tag);
-  if (maxp <= 5) return go<TR, NBUF, CAP, PC, 5, true, 2>(a, G, st, tag);
-  return go<TR, NBUF, CAP, PC, 10, true, 2>(a, G, st, tag);
+  if (maxp <= 2) return GO(2, true, 2);
+  if (maxp <= 5) return GO(5, true, 2);
+  if (maxp <= 7) return GO(7, true, 2);
+  return GO(9, true, 2);
+#undef GO
 }
 
 }  // namespace p16
@@ -508,19 +567,18 @@ hipError_t launch_pass16(const PassArgs<double>& pa, int64_t m, hipStream_t st,
   const int ntb = pa.gram ? pa.gbn_p / 16 : 1;
   if (ntb > 2) return hipErrorNotSupported;
   const int npairs = pa.gram ? (pa.ga_p / 16) * ntb : 0;
-  const int maxp = (npairs + kNW - 1) / kNW;
-  if (maxp > 10) return hipErrorNotSupported;
   int pick = -1;
   if (const char* env = getenv("BCGS_PASS16_SHAPE")) {
     const int f = atoi(env);
     if (f >= 0 && f < kNShapes &&
-        shape_fits(kShapes[f], pa.ncols_p, shared, maxp))
+        shape_fits(kShapes[f], pa.ncols_p, shared, npairs))
       pick = f;
   }
   for (int i = 0; pick < 0 && i < kNShapes; ++i)
-    if (shape_fits(kShapes[i], pa.ncols_p, shared, maxp)) pick = i;
+    if (shape_fits(kShapes[i], pa.ncols_p, shared, npairs)) pick = i;
   if (pick < 0) return hipErrorNotSupported;
   const Shape sh = kShapes[pick];
+  const int maxp = shape_maxp(sh, npairs);
   Args a{};
   // rows split over 256 * per_cu workgroups (256 CUs on MI355X)
   const int64_t rpw = round_up64(cdiv(m, 256 * sh.per_cu), 64);
@@ -540,12 +598,14 @@ hipError_t launch_pass16(const PassArgs<double>& pa, int64_t m, hipStream_t st,
   *G_out = G;
   const bool gram = pa.gram;
   switch (pick) {
-    case 0: return go_shape<64, 2, 64, 2>(a, G, gram, ntb, maxp, st, tag);
-    case 1: return go_shape<32, 2, 128, 2>(a, G, gram, ntb, maxp, st, tag);
-    case 2: return go_shape<16, 2, 272, 2>(a, G, gram, ntb, maxp, st, tag);
-    case 3: return go_shape<16, 4, 272, 1>(a, G, gram, ntb, maxp, st, tag);
-    case 4: return go_shape<64, 4, 64, 1>(a, G, gram, ntb, maxp, st, tag);
-    case 5: return go_shape<32, 4, 128, 1>(a, G, gram, ntb, maxp, st, tag);
+#define SH(i, ...) case i: return go_shape<__VA_ARGS__>(a, G, gram, ntb, maxp, st, tag);
+    SH(0, 64, 2, 64, 2, 4, false)
+    SH(1, 32, 2, 128, 2, 4, false)
+    SH(2, 16, 2, 272, 2, 4, false)
+    SH(3, 16, 4, 272, 1, 4, true)
+    SH(4, 16, 3, 272, 1, 8, true)
+    SH(5, 16, 4, 272, 1, 8, false)
+#undef SH
   }
   return hipErrorNotSupported;
 }
