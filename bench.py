@@ -109,7 +109,8 @@ def kernel_name(kind, tag):
         nw, pc = (tag // 100000000) % 10, (tag // 10000000) % 10
         nbuf, scr2 = (tag // 1000000) % 10, (tag // 100000) % 10
         tr, maxp, ntb = (tag // 1000) % 100, (tag // 10) % 100, tag % 10
-        cap = {64: 64, 32: 128, 16: 272}.get(tr, 0)
+        cap = {(64, 4): 64, (64, 8): 128, (32, 4): 128, (32, 8): 272,
+               (16, 4): 272, (16, 8): 272}.get((tr, nw), 0)
         gram = "true" if ntb else "false"
         if pc == 2:
             return (f"pass16_kernel<{tr}, {nbuf}, {cap}, {maxp}, {gram}, "
@@ -118,8 +119,9 @@ def kernel_name(kind, tag):
                 f"{'true' if scr2 else 'false'}, {maxp}, {gram}, "
                 f"{max(ntb, 1)}>")
     if kind == "pass":
-        gram, ntb, maxa = tag // 100, (tag // 10) % 10, tag % 10
-        return (f"pass_kernel<double,{'true' if gram else 'false'},{ntb},"
+        t = "float" if tag >= 1000 else "double"
+        gram, ntb, maxa = (tag // 100) % 10, (tag // 10) % 10, tag % 10
+        return (f"pass_kernel<{t},{'true' if gram else 'false'},{ntb},"
                 f"{maxa}>")
     return {"reduce": "gram_reduce_kernel", "epilogue": "epilogue_kernel",
             "tsqr_leaf": "tsqr_leaf_kernel<double>",

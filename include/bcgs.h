@@ -133,8 +133,72 @@ int32_t bcgs_sync_count(int64_t m, int64_t n, int64_t s,
  * ran on the stream. */
 bcgs_status bcgs_get_info(hipStream_t stream, bcgs_info* host_out);
 
-/* Frees the library-owned workspaces of every stream (waits for them). */
+/* Frees the library-owned workspaces of every stream, the batch arenas,
+ * cached graphs and library streams (waits for them). */
 void bcgs_release(void);
+
+/* ---- many problems in one launch -----------------------------------------
+ * Independent factorizations (each exactly the computation bcgs_qr_ex does
+ * for it: same variant, same kernels, same bits) enqueued together. */
+typedef struct {
+    const void* X;       /* m x n, ld ldx; binary64 or binary32 (precision) */
+    void* Q;             /* m x n output, ld ldq, same element type as X */
+    double* R;           /* n x n output, ld ldr */
+    int64_t m, n, s, ldx, ldq, ldr;
+    int32_t variant;     /* bcgs_variant */
+    int32_t precision;   /* bcgs_precision */
+    bcgs_info* d_info;   /* device, one record per problem */
+} bcgs_problem;
+
+/* Enqueue `count` problems (host array) on `stream` as one launch of a HIP
+ * graph: every problem's schedule runs on one of a fixed set of library
+ * streams forked from `stream` (largest modelled work first, each to the
+ * least loaded branch) and joined back, so independent problems overlap on
+ * the device.  The instantiated graph is cached per stream and replayed
+ * while the problem array (pointers, shapes, tuned choices) is unchanged.
+ * Workspace is library-owned (one arena per stream, grown on demand; freed
+ * by bcgs_release).  Problems must not share Q, R or d_info.
+ * Returns BCGS_ERR_ARG (nothing enqueued) if any problem fails the checks
+ * of bcgs_qr_ex, BCGS_ERR_NOMEM if the arena cannot grow, BCGS_ERR_HIP on a
+ * runtime failure, BCGS_OK otherwise (count == 0 enqueues nothing).
+ * Environment BCGS_BATCH_MODE=streams enqueues the same branches directly,
+ * without the graph (for comparison). */
+bcgs_status bcgs_qr_batched(const bcgs_problem* probs, int32_t count,
+                            hipStream_t stream);
+
+/* Launch choices of one problem class.  Problem classes are keyed by
+ * (floor(log2 m), n, s, variant, precision); every entry point reads the
+ * same process-wide table, so a problem alone, batched or queued runs the
+ * same kernels and gives the same bits.
+ *   max_wg  upper bound on the workgroups (row ranges) of a streaming pass,
+ *           1..512; fewer cut the partial-sum traffic of short matrices
+ *   shape   tile shape index of the s <= 16 FP64 pass, -1 = automatic */
+typedef struct {
+    int32_t max_wg;
+    int32_t shape;
+} bcgs_tuning;
+
+/* Autotuner: for every problem whose class has no entry yet, time each
+ * candidate choice on that problem (HIP events on `stream`, best of two
+ * runs after a warm-up; first max_wg in 512, 256, ..., 16, then shape) and
+ * store the fastest.  Writes the problems' Q, R and d_info as a side effect
+ * and synchronizes `stream`.  BCGS_ERR_ARG as bcgs_qr_batched. */
+bcgs_status bcgs_autotune(const bcgs_problem* probs, int32_t count,
+                          hipStream_t stream);
+
+/* Read the entry of a class: BCGS_OK (filled), BCGS_PENDING (no entry; the
+ * defaults max_wg = 512, shape = -1 are filled), BCGS_ERR_ARG. */
+bcgs_status bcgs_tuning_get(int64_t m, int64_t n, int64_t s,
+                            bcgs_variant variant, bcgs_precision precision,
+                            bcgs_tuning* out);
+
+/* Set (choice != NULL) or erase (choice == NULL) the entry of a class. */
+bcgs_status bcgs_tuning_set(int64_t m, int64_t n, int64_t s,
+                            bcgs_variant variant, bcgs_precision precision,
+                            const bcgs_tuning* choice);
+
+/* Erase every entry. */
+void bcgs_tuning_clear(void);
 
 /* ---- launch profiling ----------------------------------------------------
  * Between bcgs_profile_start(stream) and bcgs_profile_stop(stream, ...), every
@@ -154,8 +218,12 @@ enum {
     BCGS_KERNEL_OTHER = 7
 };
 
-/* One profiled launch.  tag identifies the kernel instantiation (for
- * BCGS_KERNEL_PASS: 100*gram + 10*B tiles + A tiles per wave). */
+/* One profiled launch.  tag identifies the kernel instantiation.  For
+ * BCGS_KERNEL_PASS, tags >= 10^9 are the s <= 16 pass, decimal digits
+ * 1 W P B S TT PP N (waves, workgroups per CU, tile buffers, second partial
+ * area, tile rows, Gram pairs per wave, Gram B blocks); smaller tags are the
+ * general pass, 1000*(binary32) + 100*gram + 10*B blocks + A blocks per
+ * wave. */
 typedef struct {
     int32_t kind;
     int32_t tag;

@@ -44,6 +44,23 @@ class LaunchRecord(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("tag", ctypes.c_int32),
                 ("ms", ctypes.c_double), ("bytes", ctypes.c_double),
                 ("flops", ctypes.c_double)]
+
+
+class Problem(ctypes.Structure):
+    """Mirror of bcgs_problem."""
+    _fields_ = [("X", ctypes.c_void_p), ("Q", ctypes.c_void_p),
+                ("R", ctypes.c_void_p), ("m", ctypes.c_int64),
+                ("n", ctypes.c_int64), ("s", ctypes.c_int64),
+                ("ldx", ctypes.c_int64), ("ldq", ctypes.c_int64),
+                ("ldr", ctypes.c_int64), ("variant", ctypes.c_int32),
+                ("precision", ctypes.c_int32), ("d_info", ctypes.c_void_p)]
+
+
+class Tuning(ctypes.Structure):
+    """Mirror of bcgs_tuning."""
+    _fields_ = [("max_wg", ctypes.c_int32), ("shape", ctypes.c_int32)]
+
+
 _lib = None
 
 _PROTOS = {
@@ -66,6 +83,17 @@ _PROTOS = {
     "bcgs_get_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Info)]),
     "bcgs_release": (None, []),
     "bcgs_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+    "bcgs_qr_batched": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32,
+                                       ctypes.c_void_p]),
+    "bcgs_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32,
+                                     ctypes.c_void_p]),
+    "bcgs_tuning_get": (ctypes.c_int, [ctypes.c_int64, ctypes.c_int64,
+                                       ctypes.c_int64, ctypes.c_int,
+                                       ctypes.c_int, ctypes.c_void_p]),
+    "bcgs_tuning_set": (ctypes.c_int, [ctypes.c_int64, ctypes.c_int64,
+                                       ctypes.c_int64, ctypes.c_int,
+                                       ctypes.c_int, ctypes.c_void_p]),
+    "bcgs_tuning_clear": (None, []),
     "bcgs_profile_start": (ctypes.c_int, [ctypes.c_void_p]),
     "bcgs_profile_stop": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p,
                                            ctypes.c_int32]),
@@ -207,3 +235,83 @@ def get_info(stream=None):
     if st != BCGS_OK:
         raise BcgsError(st, "bcgs_get_info")
     return info
+
+
+class Batch:
+    """A list of problems with device outputs and one info record each, in
+    the layout bcgs_qr_batched takes.  Keeps the tensors alive."""
+
+    def __init__(self, items, device="cuda"):
+        """items: iterable of (X, s, variant, precision) with X a column-major
+        device tensor (float64 for fp64, float32 for fp32-bulk)."""
+        import torch
+        self.items = []
+        arr = []
+        self.info_buf = None
+        items = list(items)
+        self.info_buf = torch.zeros(max(1, len(items)) * INFO_BYTES,
+                                    dtype=torch.uint8, device=device)
+        for i, (X, s, variant, precision) in enumerate(items):
+            m, n = X.shape
+            ldx = _col_major(X, "X")
+            want = torch.float64 if precision == "fp64" else torch.float32
+            if X.dtype != want:
+                raise ValueError(f"X must be {want} for precision {precision}")
+            Q = empty_fortran(m, n, want, X.device)
+            R = empty_fortran(n, n, torch.float64, X.device)
+            self.items.append((X, Q, R, s, variant, precision))
+            arr.append(Problem(X.data_ptr(), Q.data_ptr(), R.data_ptr(), m, n,
+                               s, ldx, Q.stride(1), R.stride(1),
+                               VARIANTS[variant], PRECISIONS[precision],
+                               self.info_buf.data_ptr() + i * INFO_BYTES))
+        self.array = (Problem * max(1, len(arr)))(*arr)
+        self.count = len(arr)
+
+    def results(self):
+        """[(Q, R, Info)] in input order (synchronizes on the info copy)."""
+        raw = self.info_buf.cpu().numpy().tobytes()
+        return [(Q, R, Info.from_buffer_copy(raw[i * INFO_BYTES:
+                                                 (i + 1) * INFO_BYTES]))
+                for i, (_, Q, R, *_r) in enumerate(self.items)]
+
+
+def qr_batched(batch, stream=None):
+    """Enqueue every problem of `batch` (a Batch) as one graph launch."""
+    st = lib().bcgs_qr_batched(ctypes.byref(batch.array), batch.count,
+                               _stream_handle(stream))
+    if st != BCGS_OK:
+        raise BcgsError(st, "bcgs_qr_batched")
+    return batch
+
+
+def autotune(batch, stream=None):
+    """Tune every problem class of `batch` that has no entry yet."""
+    st = lib().bcgs_autotune(ctypes.byref(batch.array), batch.count,
+                             _stream_handle(stream))
+    if st != BCGS_OK:
+        raise BcgsError(st, "bcgs_autotune")
+
+
+def tuning_get(m, n, s, variant, precision="fp64"):
+    """(max_wg, shape, tuned) of a problem class."""
+    t = Tuning()
+    st = lib().bcgs_tuning_get(m, n, s, VARIANTS[variant],
+                               PRECISIONS[precision], ctypes.byref(t))
+    if st not in (BCGS_OK, 6):
+        raise BcgsError(st, "bcgs_tuning_get")
+    return t.max_wg, t.shape, st == BCGS_OK
+
+
+def tuning_set(m, n, s, variant, precision="fp64", max_wg=None, shape=-1):
+    """Set the entry of a class (max_wg None erases it)."""
+    ptr = None
+    if max_wg is not None:
+        ptr = ctypes.byref(Tuning(max_wg, shape))
+    st = lib().bcgs_tuning_set(m, n, s, VARIANTS[variant],
+                               PRECISIONS[precision], ptr)
+    if st != BCGS_OK:
+        raise BcgsError(st, "bcgs_tuning_set")
+
+
+def tuning_clear():
+    lib().bcgs_tuning_clear()

@@ -89,6 +89,15 @@ struct TsqrPlan {
 TsqrPlan make_tsqr_plan(int64_t m, int s);
 
 // ------------------------------------------------------- workspace plan ---
+// Launch choices that the autotuner may set per problem class.  They change
+// the row split (and so the order of the cross-workgroup sums) and the tile
+// shape, never the method: results stay within the stated tolerances and
+// are bitwise repeatable for a fixed choice.
+struct Tuning {
+  int max_wg = 512;   // upper bound on the workgroups of a streaming pass
+  int shape = -1;     // pass16 tile shape index, -1 = automatic
+};
+
 struct Plan {
   int64_t m, n;
   int s, sp, q;
@@ -96,6 +105,7 @@ struct Plan {
   int G;                  // workgroups (row ranges) of the streaming passes
   int64_t rows_per_wg;
   int tr_max;             // largest tile the widest pass can afford
+  Tuning tune;
   TsqrPlan tsqr;
   // workspace offsets in bytes
   size_t off_c1, off_c2, off_t1, off_t2, off_f1, off_f2, off_gram,
@@ -107,7 +117,27 @@ struct Plan {
 };
 
 bool make_plan(int64_t m, int64_t n, int64_t s, int variant, int precision,
-               Plan* p);
+               Plan* p, const Tuning* t = nullptr);
+
+// Process-wide table of tuned choices, keyed by problem class (see tune.hip);
+// every entry point consults it, so a problem run alone, batched or served
+// takes the same choices and gives the same bits.
+bool tuned_choice(int64_t m, int64_t n, int s, int variant, int precision,
+                  Tuning* out);
+
+// Argument checks shared by every entry point (BCGS_ERR_ARG before anything
+// is enqueued); fills the plan with the tuned choices of the problem class.
+bcgs_status check_problem(const void* X, int64_t ldx, int64_t m, int64_t n,
+                          int64_t s, int variant, int precision,
+                          const void* Q, int64_t ldq, const double* R,
+                          int64_t ldr, const bcgs_info* d_info, Plan* p);
+// Frees the batch arenas, cached graphs and library streams (batch.hip).
+void batch_release();
+
+// Enqueue the whole factorization on `st` (workspace of p.bytes bytes).
+bcgs_status run_problem(const Plan& p, const void* X, int64_t ldx, void* Q,
+                        int64_t ldq, double* R, int64_t ldr, void* ws,
+                        bcgs_info* info, hipStream_t st);
 
 // Launchers (return hipError_t of the launch).
 // *tag receives the kernel instantiation (see bcgs_launch_record).
@@ -118,7 +148,9 @@ hipError_t launch_gram_reduce(const double* partial, int G, int64_t elems,
 // Fast path for s <= 16 (pass16.hip); hipErrorNotSupported when it does not
 // apply (nothing launched).
 hipError_t launch_pass16(const PassArgs<double>& a, int64_t m,
-                         hipStream_t st, int* tag, int* G_out);
+                         const Tuning& tune, hipStream_t st, int* tag,
+                         int* G_out);
+int pass16_shape_count();
 size_t pass16_lds_bytes(int ncols_p, int tr, int nw);
 
 struct EpiArgs;

@@ -46,13 +46,15 @@ static bool valid_args(int64_t m, int64_t n, int64_t s, int variant,
 static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 bool make_plan(int64_t m, int64_t n, int64_t s, int variant, int precision,
-               Plan* p) {
+               Plan* p, const Tuning* t) {
   if (!valid_args(m, n, s, variant, precision)) return false;
   Plan P{};
   P.m = m; P.n = n; P.s = (int)s; P.sp = round_up((int)s, 16);
   P.q = (int)(n / s);
   P.variant = variant; P.precision = precision;
-  const int64_t target_wg = 512;
+  if (t) P.tune = *t;
+  if (P.tune.max_wg < 1 || P.tune.max_wg > 512) return false;
+  const int64_t target_wg = P.tune.max_wg;
   P.rows_per_wg = round_up64(cdiv(m, target_wg), 64);
   P.G = (int)cdiv(m, P.rows_per_wg);
   P.gram_ld = round_up64(n + s, 16);
@@ -201,12 +203,12 @@ struct Run {
     int tag = 0;
     prof_begin(BCGS_KERNEL_PASS, -1, esz * mr * cols_rw, flops);
     hipError_t e = hipErrorNotSupported;
-    if (sizeof(T) == 8 && p.sp == 16) {
-      PassArgs<double> b;
-      memcpy(&b, &a, sizeof(b));
-      int g16 = 0;
-      e = launch_pass16(b, p.m, st, &tag, &g16);
-      if (e != hipErrorNotSupported) G = g16;
+    if constexpr (sizeof(T) == 8) {
+      if (p.sp == 16) {
+        int g16 = 0;
+        e = launch_pass16(a, p.m, p.tune, st, &tag, &g16);
+        if (e != hipErrorNotSupported) G = g16;
+      }
     }
     if (e == hipErrorNotSupported) e = launch_pass(a, G, st, &tag);
     check(e);
@@ -355,6 +357,43 @@ static bcgs_status run_plan(const Plan& p, const T* X, int64_t ldx, T* Q,
   return r.err == hipSuccess ? BCGS_OK : BCGS_ERR_HIP;
 }
 
+bcgs_status run_problem(const Plan& p, const void* X, int64_t ldx, void* Q,
+                        int64_t ldq, double* R, int64_t ldr, void* ws,
+                        bcgs_info* info, hipStream_t st) {
+  if (p.precision == BCGS_FP32_BULK)
+    return run_plan<float>(p, static_cast<const float*>(X), ldx,
+                           static_cast<float*>(Q), ldq, R, ldr, ws, info, st);
+  return run_plan<double>(p, static_cast<const double*>(X), ldx,
+                          static_cast<double*>(Q), ldq, R, ldr, ws, info, st);
+}
+
+static bool overlaps(const void* a, size_t an, const void* b, size_t bn) {
+  const char* pa = static_cast<const char*>(a);
+  const char* pb = static_cast<const char*>(b);
+  return pa < pb + bn && pb < pa + an;
+}
+
+bcgs_status check_problem(const void* X, int64_t ldx, int64_t m, int64_t n,
+                          int64_t s, int variant, int precision,
+                          const void* Q, int64_t ldq, const double* R,
+                          int64_t ldr, const bcgs_info* d_info, Plan* p) {
+  if (!X || !Q || !R || !d_info) return BCGS_ERR_ARG;
+  if (!valid_args(m, n, s, variant, precision)) return BCGS_ERR_ARG;
+  if (ldx < m || ldq < m || ldr < n) return BCGS_ERR_ARG;
+  Tuning t;
+  const bool tuned = tuned_choice(m, n, (int)s, variant, precision, &t);
+  if (!make_plan(m, n, s, variant, precision, p, tuned ? &t : nullptr))
+    return BCGS_ERR_ARG;
+  const size_t esz = precision == BCGS_FP64 ? 8 : 4;
+  const size_t xbytes = (size_t)((n - 1) * ldx + m) * esz;
+  const size_t qbytes = (size_t)((n - 1) * ldq + m) * esz;
+  const size_t rbytes = (size_t)((n - 1) * ldr + n) * 8;
+  if (overlaps(X, xbytes, Q, qbytes)) return BCGS_ERR_ARG;
+  if (overlaps(R, rbytes, Q, qbytes) || overlaps(R, rbytes, X, xbytes))
+    return BCGS_ERR_ARG;
+  return BCGS_OK;
+}
+
 // --------------------------------------------------- library workspace ---
 struct StreamWs {
   void* ptr = nullptr;
@@ -363,12 +402,6 @@ struct StreamWs {
 };
 static std::mutex g_mu;
 static std::map<hipStream_t, StreamWs> g_ws;
-
-static bool overlaps(const void* a, size_t an, const void* b, size_t bn) {
-  const char* pa = static_cast<const char*>(a);
-  const char* pb = static_cast<const char*>(b);
-  return pa < pb + bn && pb < pa + an;
-}
 
 }  // namespace bcgs
 
@@ -396,22 +429,12 @@ bcgs_status bcgs_qr_ex(const void* X, int64_t ldx, int64_t m, int64_t n,
                        size_t ws_bytes, bcgs_info* d_info,
                        hipStream_t stream) {
   Plan p;
-  if (!X || !Q || !R || !workspace || !d_info) return BCGS_ERR_ARG;
-  if (!make_plan(m, n, s, variant, precision, &p)) return BCGS_ERR_ARG;
-  if (ldx < m || ldq < m || ldr < n) return BCGS_ERR_ARG;
-  if (ws_bytes < p.bytes) return BCGS_ERR_ARG;
+  const bcgs_status st = check_problem(X, ldx, m, n, s, variant, precision, Q,
+                                       ldq, R, ldr, d_info, &p);
+  if (st != BCGS_OK) return st;
+  if (!workspace || ws_bytes < p.bytes) return BCGS_ERR_ARG;
   if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0) return BCGS_ERR_ARG;
-  const size_t esz = precision == BCGS_FP64 ? 8 : 4;
-  const size_t xbytes = (size_t)((n - 1) * ldx + m) * esz;
-  const size_t qbytes = (size_t)((n - 1) * ldq + m) * esz;
-  if (overlaps(X, xbytes, Q, qbytes)) return BCGS_ERR_ARG;
-  if (overlaps(R, (size_t)((n - 1) * ldr + n) * 8, Q, qbytes) ||
-      overlaps(R, (size_t)((n - 1) * ldr + n) * 8, X, xbytes))
-    return BCGS_ERR_ARG;
-  if (precision == BCGS_FP32_BULK) return BCGS_ERR_UNSUPPORTED;
-  return run_plan<double>(p, static_cast<const double*>(X), ldx,
-                          static_cast<double*>(Q), ldq, R, ldr, workspace,
-                          d_info, stream);
+  return run_problem(p, X, ldx, Q, ldq, R, ldr, workspace, d_info, stream);
 }
 
 bcgs_status bcgs_qr(const double* X, int64_t m, int64_t n, int64_t s,
@@ -419,7 +442,13 @@ bcgs_status bcgs_qr(const double* X, int64_t m, int64_t n, int64_t s,
                     hipStream_t stream) {
   Plan p;
   if (!X || !Q || !R) return BCGS_ERR_ARG;
-  if (!make_plan(m, n, s, variant, BCGS_FP64, &p)) return BCGS_ERR_ARG;
+  {
+    Tuning t;
+    const bool tuned = valid_args(m, n, s, variant, BCGS_FP64) &&
+                       tuned_choice(m, n, (int)s, variant, BCGS_FP64, &t);
+    if (!make_plan(m, n, s, variant, BCGS_FP64, &p, tuned ? &t : nullptr))
+      return BCGS_ERR_ARG;
+  }
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return BCGS_ERR_HIP;
   void* ws = nullptr;
@@ -465,6 +494,7 @@ bcgs_status bcgs_get_info(hipStream_t stream, bcgs_info* host_out) {
 }
 
 void bcgs_release(void) {
+  batch_release();
   std::lock_guard<std::mutex> lock(g_mu);
   for (auto& kv : g_ws) {
     if (kv.second.ptr) {

@@ -17,18 +17,41 @@
 // The partial Gram matrices of all workgroups are then summed in a fixed
 // order by gram_reduce_kernel, so results do not depend on timing.
 //
-// MFMA v_mfma_f64_16x16x4f64 operand layout (lane l of 64):
+// The tile, the products and the per-workgroup partial sums are in the
+// storage type T: FP64 for the FP64 form, FP32 for the FP32-bulk form
+// (whose partials are widened to FP64 before the cross-workgroup sum).
+//
+// MFMA 16x16x4 operand layout (lane l of 64), FP64 and FP32 alike:
 //   A (16 x 4): A[l % 16][l / 16]     B (4 x 16): B[l / 16][l % 16]
-//   D (16 x 16), 4 values v:          D[l / 16 + 4 * v][l % 16]
+// Result D (16 x 16), 4 values v per lane, column l % 16, row
+//   FP64 (v_mfma_f64_16x16x4f64): l / 16 + 4 v
+//   FP32 (v_mfma_f32_16x16x4f32): 4 (l / 16) + v
 #include "common.h"
 
 namespace bcgs {
 
 typedef double v4d __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
 
-__device__ __forceinline__ v4d mfma_f64(double a, double b, v4d c) {
-  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-}
+template <typename T> struct Mma;
+template <> struct Mma<double> {
+  typedef v4d acc;
+  static __device__ __forceinline__ v4d mac(double a, double b, v4d c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int lk, int v) {
+    return lk + 4 * v;
+  }
+};
+template <> struct Mma<float> {
+  typedef v4f acc;
+  static __device__ __forceinline__ v4f mac(float a, float b, v4f c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int lk, int v) {
+    return 4 * lk + v;
+  }
+};
 
 template <typename T>
 __device__ __forceinline__ const T* col_src(const PassArgs<T>& a, int c,
@@ -55,8 +78,8 @@ __device__ __forceinline__ int update_ksplit(int tr, int sp) {
 }
 
 template <typename T>
-__device__ void update_partials(const PassArgs<T>& a, const double* tile,
-                                int trp, double* scr, int uc0,
+__device__ void update_partials(const PassArgs<T>& a, const T* tile,
+                                int trp, T* scr, int uc0,
                                 const double* __restrict__ F) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int tr = a.tr, sp = a.sp, s = a.s;
@@ -70,37 +93,37 @@ __device__ void update_partials(const PassArgs<T>& a, const double* tile,
   for (int task = wave; task < nt * ksplit; task += kWaves) {
     const int t = task % nt, ks = task / nt;
     const int rb = t % mb, cb = t / mb;
-    v4d acc = {0.0, 0.0, 0.0, 0.0};
+    typename Mma<T>::acc acc = {0, 0, 0, 0};
     const int kb = ks * kper, ke = min(ksteps, kb + kper);
     for (int kk = kb; kk < ke; ++kk) {
       const int k = kk * 4 + lk;
-      double av = 0.0, bv = 0.0;
+      T av = 0, bv = 0;
       if (k < K) {
         av = tile[k * trp + rb * 16 + li];
-        bv = F[k * sp + cb * 16 + li];
+        bv = static_cast<T>(F[k * sp + cb * 16 + li]);
       }
-      acc = mfma_f64(av, bv, acc);
+      acc = Mma<T>::mac(av, bv, acc);
     }
-    double* out = scr + (size_t)ks * tr * srow;
+    T* out = scr + (size_t)ks * tr * srow;
 #pragma unroll
     for (int v = 0; v < 4; ++v)
-      out[(rb * 16 + lk + 4 * v) * srow + cb * 16 + li] = acc[v];
+      out[(rb * 16 + Mma<T>::row(lk, v)) * srow + cb * 16 + li] = acc[v];
   }
 }
 
 template <typename T>
-__device__ void update_finish(const PassArgs<T>& a, double* tile, int trp,
-                              const double* scr, int uc0, T* dst,
+__device__ void update_finish(const PassArgs<T>& a, T* tile, int trp,
+                              const T* scr, int uc0, T* dst,
                               int64_t ldd, int64_t r0, int rows) {
   const int tr = a.tr, s = a.s, srow = a.sp + 1;
   const int ksplit = update_ksplit(tr, a.sp);
   for (int e = threadIdx.x; e < tr * s; e += kThreads) {
     const int r = e % tr, c = e / tr;
-    double sum = 0.0;
+    T sum = 0;
     for (int ks = 0; ks < ksplit; ++ks)
       sum += scr[(size_t)ks * tr * srow + r * srow + c];
     tile[(uc0 + c) * trp + r] = sum;
-    if (r < rows) dst[(int64_t)c * ldd + r0 + r] = static_cast<T>(sum);
+    if (r < rows) dst[(int64_t)c * ldd + r0 + r] = sum;
   }
 }
 
@@ -108,8 +131,8 @@ template <typename T, bool GRAM, int NTB, int MAXA>
 __global__ __launch_bounds__(kThreads) void pass_kernel(PassArgs<T> a) {
   extern __shared__ double lds[];
   const int tr = a.tr, trp = tr + 1;
-  double* tile = lds;
-  double* scr = tile + (size_t)a.ncols_p * trp;
+  T* tile = reinterpret_cast<T*>(lds);
+  T* scr = tile + (size_t)a.ncols_p * trp;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int li = lane & 15, lk = lane >> 4;
   const int h = blockIdx.x % a.groups;
@@ -118,7 +141,7 @@ __global__ __launch_bounds__(kThreads) void pass_kernel(PassArgs<T> a) {
   const int64_t row_end = min(a.m, row_begin + a.rows_per_wg);
 
 
-  v4d acc[MAXA][NTB];
+  typename Mma<T>::acc acc[MAXA][NTB];
   int ta_of[MAXA];
   const int ta_total = a.ga_p >> 4;
   const int ta_lo = h * a.a_blocks_per_group;
@@ -127,7 +150,7 @@ __global__ __launch_bounds__(kThreads) void pass_kernel(PassArgs<T> a) {
   for (int i = 0; i < MAXA; ++i) {
     ta_of[i] = ta_lo + wave + kWaves * i;
 #pragma unroll
-    for (int b = 0; b < NTB; ++b) acc[i][b] = v4d{0.0, 0.0, 0.0, 0.0};
+    for (int b = 0; b < NTB; ++b) acc[i][b] = typename Mma<T>::acc{0, 0, 0, 0};
   }
   __syncthreads();
 
@@ -138,18 +161,18 @@ __global__ __launch_bounds__(kThreads) void pass_kernel(PassArgs<T> a) {
     // 1. stage the column window (zero past m and past ncols)
     for (int idx = tid; idx < nstage; idx += kThreads) {
       const int c = idx >> tr_shift, r = idx & (tr - 1);
-      double v = 0.0;
+      T v = 0;
       if (r < rows && c < a.ncols) {
         int64_t ld;
         const T* src = col_src(a, c, &ld);
-        v = static_cast<double>(src[r0 + r]);
+        v = src[r0 + r];
       }
       tile[c * trp + r] = v;
     }
     __syncthreads();
     // 2-3. block updates, both on the staged columns
     if (a.upd1 || a.upd2) {
-      double* scr2 = a.upd1 ? scr + (size_t)update_ksplit(tr, a.sp) * tr *
+      T* scr2 = a.upd1 ? scr + (size_t)update_ksplit(tr, a.sp) * tr *
                                         (a.sp + 1)
                             : scr;
       if (a.upd1) update_partials(a, tile, trp, scr, a.u1_c0, a.c1);
@@ -165,7 +188,7 @@ __global__ __launch_bounds__(kThreads) void pass_kernel(PassArgs<T> a) {
     if (GRAM) {
       for (int kk = 0; kk < tr; kk += 4) {
         const int r = kk + lk;
-        double bf[NTB];
+        T bf[NTB];
 #pragma unroll
         for (int b = 0; b < NTB; ++b)
           bf[b] = tile[(a.gb0 + b * 16 + li) * trp + r];
@@ -173,11 +196,11 @@ __global__ __launch_bounds__(kThreads) void pass_kernel(PassArgs<T> a) {
         for (int i = 0; i < MAXA; ++i) {
           const int ta = ta_of[i];
           if (ta < ta_hi) {
-            const double af = tile[(ta * 16 + li) * trp + r];
+            const T af = tile[(ta * 16 + li) * trp + r];
 #pragma unroll
             for (int b = 0; b < NTB; ++b) {
               if (ta * 16 >= a.skip_a0 && b * 16 + 16 <= a.skip_b1) continue;
-              acc[i][b] = mfma_f64(af, bf[b], acc[i][b]);
+              acc[i][b] = Mma<T>::mac(af, bf[b], acc[i][b]);
             }
           }
         }
@@ -196,8 +219,8 @@ __global__ __launch_bounds__(kThreads) void pass_kernel(PassArgs<T> a) {
       for (int b = 0; b < NTB; ++b) {
 #pragma unroll
         for (int v = 0; v < 4; ++v)
-          out[(size_t)(b * 16 + li) * a.ga_p + ta * 16 + lk + 4 * v] =
-              acc[i][b][v];
+          out[(size_t)(b * 16 + li) * a.ga_p + ta * 16 + Mma<T>::row(lk, v)] =
+              static_cast<double>(acc[i][b][v]);
       }
     }
   }
@@ -257,13 +280,13 @@ size_t pass_lds_bytes(const PassArgs<T>& a) {
   const int nupd = (a.upd1 ? 1 : 0) + (a.upd2 ? 1 : 0);
   size_t d = (size_t)a.ncols_p * (a.tr + 1) +
              (size_t)(nupd > 1 ? 2 : 1) * ksplit * a.tr * (a.sp + 1);
-  return d * sizeof(double);
+  return d * sizeof(T);
 }
 
 template <typename T, bool GRAM, int NTB, int MAXA>
 static hipError_t launch_one(const PassArgs<T>& a, int G, hipStream_t st,
                              int* tag) {
-  *tag = (GRAM ? 100 : 0) + 10 * NTB + MAXA;
+  *tag = (sizeof(T) == 4 ? 1000 : 0) + (GRAM ? 100 : 0) + 10 * NTB + MAXA;
   auto kern = pass_kernel<T, GRAM, NTB, MAXA>;
   const size_t lds = pass_lds_bytes(a);
   static bool attr_done = false;
@@ -298,5 +321,8 @@ hipError_t launch_pass(const PassArgs<T>& a, int G, hipStream_t st,
 template hipError_t launch_pass<double>(const PassArgs<double>&, int,
                                         hipStream_t, int*);
 template size_t pass_lds_bytes<double>(const PassArgs<double>&);
+template hipError_t launch_pass<float>(const PassArgs<float>&, int,
+                                       hipStream_t, int*);
+template size_t pass_lds_bytes<float>(const PassArgs<float>&);
 
 }  // namespace bcgs

@@ -499,11 +499,15 @@ static hipError_t go(const Args& a, int G, hipStream_t st, int* tag) {
 // partial-sum areas)
 struct Shape { int tr, nbuf, cap, per_cu, nw, scr2; };
 
-// in order of preference; BCGS_PASS16_SHAPE=<index> forces one (tuning).
-// launch_pass16's switch instantiates the same list, entry by entry.
+// launch_pass16 picks among these (or takes the tuned / BCGS_PASS16_SHAPE
+// index); its switch instantiates the same list, entry by entry.
+// Taller tiles stream faster (each copy instruction covers fewer columns,
+// so fewer pages and longer runs per column: on MI355X about 4.2, 5.7 and
+// 6.3 TB/s for 16, 32 and 64 rows), so wide passes take one workgroup of 8
+// waves per CU with 32- or 64-row tiles.
 constexpr Shape kShapes[] = {
-    {64, 2, 64, 2, 4, 0},  {32, 2, 128, 2, 4, 0}, {16, 2, 272, 2, 4, 0},
-    {16, 4, 272, 1, 4, 1}, {16, 3, 272, 1, 8, 1}, {16, 4, 272, 1, 8, 0}};
+    {64, 2, 64, 2, 4, 0},  {64, 2, 128, 1, 8, 0}, {32, 2, 272, 1, 8, 0},
+    {32, 2, 128, 2, 4, 0}, {16, 2, 272, 2, 4, 0}, {16, 4, 272, 1, 4, 1}};
 constexpr int kNShapes = sizeof(kShapes) / sizeof(kShapes[0]);
 
 static int shape_maxp(const Shape& sh, int npairs) {
@@ -522,17 +526,29 @@ template <int TR, int NBUF, int CAP, int PC, int NW, bool SCR2>
 static hipError_t go_shape(const Args& a, int G, bool gram, int ntb,
                            int maxp, hipStream_t st, int* tag) {
 #define GO(M_, G_, N_) go<TR, NBUF, CAP, PC, NW, SCR2, M_, G_, N_>(a, G, st, tag)
+  // largest pair count per wave this capacity can produce (two B blocks)
+  constexpr int kTop = ((CAP / 16) * 2 + NW - 1) / NW;
   if (!gram) return GO(1, false, 1);
   if (ntb == 1) {
-    if (maxp <= 2) return GO(2, true, 1);
-    if (maxp <= 5) return GO(5, true, 1);
-    if (maxp <= 7) return GO(7, true, 1);
-    return GO(9, true, 1);
+    if (kTop <= 2 || maxp <= 2) return GO(2, true, 1);
+    if constexpr (kTop > 2) {
+      if (kTop <= 5 || maxp <= 5) return GO(5, true, 1);
+      if constexpr (kTop > 5) {
+        if (kTop <= 7 || maxp <= 7) return GO(7, true, 1);
+        if constexpr (kTop > 7) return GO(9, true, 1);
+      }
+    }
+  } else {
+    if (kTop <= 2 || maxp <= 2) return GO(2, true, 2);
+    if constexpr (kTop > 2) {
+      if (kTop <= 5 || maxp <= 5) return GO(5, true, 2);
+      if constexpr (kTop > 5) {
+        if (kTop <= 7 || maxp <= 7) return GO(7, true, 2);
+        if constexpr (kTop > 7) return GO(9, true, 2);
+      }
+    }
   }
-  if (maxp <= 2) return GO(2, true, 2);
-  if (maxp <= 5) return GO(5, true, 2);
-  if (maxp <= 7) return GO(7, true, 2);
-  return GO(9, true, 2);
+  return hipErrorNotSupported;
 #undef GO
 }
 
@@ -546,8 +562,11 @@ size_t pass16_lds_bytes(int ncols_p, int tr, int nw) {
 // Returns hipErrorNotSupported (without launching) when this kernel cannot
 // take the pass.  *G_out receives the number of workgroups used (the row
 // split is a function of m and of the chosen shape only).
-hipError_t launch_pass16(const PassArgs<double>& pa, int64_t m, hipStream_t st,
-                         int* tag, int* G_out) {
+int pass16_shape_count() { return p16::kNShapes; }
+
+hipError_t launch_pass16(const PassArgs<double>& pa, int64_t m,
+                         const Tuning& tune, hipStream_t st, int* tag,
+                         int* G_out) {
   using namespace p16;
   const int s = pa.s;
   if (pa.sp != 16 || s % 4 != 0) return hipErrorNotSupported;
@@ -568,20 +587,32 @@ hipError_t launch_pass16(const PassArgs<double>& pa, int64_t m, hipStream_t st,
   if (ntb > 2) return hipErrorNotSupported;
   const int npairs = pa.gram ? (pa.ga_p / 16) * ntb : 0;
   int pick = -1;
-  if (const char* env = getenv("BCGS_PASS16_SHAPE")) {
-    const int f = atoi(env);
-    if (f >= 0 && f < kNShapes &&
-        shape_fits(kShapes[f], pa.ncols_p, shared, npairs))
-      pick = f;
+  int f = tune.shape;
+  if (f < 0) {
+    if (const char* env = getenv("BCGS_PASS16_SHAPE")) f = atoi(env);
   }
+  if (f >= 0 && f < kNShapes &&
+      shape_fits(kShapes[f], pa.ncols_p, shared, npairs))
+    pick = f;
+  // Automatic choice, measured on MI355X: passes with two B blocks of
+  // Gram (P-1S, P-2S) are bound by the MFMA work and run best with 16-row
+  // tiles, two workgroups per CU; the other wide passes are bound by the
+  // stream and take the 32-row, 8-wave shape.
+  static const int kHeavy[] = {0, 3, 4, 2, 5, 1};
+  static const int kLight[] = {0, 3, 2, 4, 5, 1};
+  const int* order = (pa.gram && ntb == 2) ? kHeavy : kLight;
   for (int i = 0; pick < 0 && i < kNShapes; ++i)
-    if (shape_fits(kShapes[i], pa.ncols_p, shared, npairs)) pick = i;
+    if (shape_fits(kShapes[order[i]], pa.ncols_p, shared, npairs))
+      pick = order[i];
   if (pick < 0) return hipErrorNotSupported;
   const Shape sh = kShapes[pick];
   const int maxp = shape_maxp(sh, npairs);
   Args a{};
-  // rows split over 256 * per_cu workgroups (256 CUs on MI355X)
-  const int64_t rpw = round_up64(cdiv(m, 256 * sh.per_cu), 64);
+  // rows split over 256 * per_cu workgroups (256 CUs on MI355X), at most
+  // tune.max_wg of them
+  const int64_t rpw =
+      std::max(round_up64(cdiv(m, 256 * sh.per_cu), 64),
+               round_up64(cdiv(m, std::max(1, tune.max_wg)), 64));
   const int G = (int)cdiv(m, rpw);
   a.m = pa.m; a.s = s; a.ncols = pa.ncols; a.ncols_p = pa.ncols_p;
   a.rows_per_wg = rpw;
@@ -600,11 +631,11 @@ hipError_t launch_pass16(const PassArgs<double>& pa, int64_t m, hipStream_t st,
   switch (pick) {
 #define SH(i, ...) case i: return go_shape<__VA_ARGS__>(a, G, gram, ntb, maxp, st, tag);
     SH(0, 64, 2, 64, 2, 4, false)
-    SH(1, 32, 2, 128, 2, 4, false)
-    SH(2, 16, 2, 272, 2, 4, false)
-    SH(3, 16, 4, 272, 1, 4, true)
-    SH(4, 16, 3, 272, 1, 8, true)
-    SH(5, 16, 4, 272, 1, 8, false)
+    SH(1, 64, 2, 128, 1, 8, false)
+    SH(2, 32, 2, 272, 1, 8, false)
+    SH(3, 32, 2, 128, 2, 4, false)
+    SH(4, 16, 2, 272, 2, 4, false)
+    SH(5, 16, 4, 272, 1, 4, true)
 #undef SH
   }
   return hipErrorNotSupported;

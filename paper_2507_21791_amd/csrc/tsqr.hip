@@ -458,5 +458,9 @@ template hipError_t launch_tsqr<double>(const TsqrPlan&, const double*,
                                         int64_t, double*, int64_t, int64_t,
                                         double*, double*, int64_t, int64_t,
                                         hipStream_t);
+template hipError_t launch_tsqr<float>(const TsqrPlan&, const float*,
+                                        int64_t, float*, int64_t, int64_t,
+                                        double*, double*, int64_t, int64_t,
+                                        hipStream_t);
 
 }  // namespace bcgs

@@ -91,3 +91,36 @@ def compare(X, s, variant, Qg, Rg, info, kappa=None, oracle_result=None):
     assert qerr <= tol_pert, (qerr, tol_pert)
     return {"loo_gpu": loo_g, "loo_oracle": loo_o, "res": res,
             "r_err": rerr, "q_err": qerr}
+
+
+U32 = 2.0 ** -24
+
+
+def compare_bulk32(X, s, variant, Qg, Rg, info, kappa):
+    """FP32-bulk result (Qg binary32 promoted, Rg binary64) against the FP64
+    oracle on the same X (X holds binary32-representable values).
+
+    The inputs are chosen inside Table 1's assumptions with u = u32 and a
+    margin (u32 kappa <= 1e-3 for BCGSI+ and P-2S, u32 kappa^2 <= 1e-2 for
+    P-1S), so no breakdown is allowed and the O(u) bounds apply with
+    u = u32:  LOO <= 10 n u32, residual <= 10 n u32, R and Q within
+    10 n u32 kappa of the FP64 oracle."""
+    m, n = X.shape
+    r = O.qr(X, s, variant)
+    assert r.breakdown is None, r.breakdown
+    assert info.status == 0, info.as_dict()
+    Rg = np.asarray(Rg)
+    Qg = np.asarray(Qg)
+    assert np.all(np.tril(Rg, -1) == 0.0), "R not upper triangular"
+    assert np.all(np.diag(Rg) > 0), "diag(R) not positive"
+    tol = 10 * n * U32
+    loo_g = O.loss_of_orthogonality(Qg)
+    assert loo_g <= tol, (loo_g, tol)
+    res = O.relative_residual(X, Qg, Rg)
+    assert res <= tol, (res, tol)
+    rerr = np.linalg.norm(Rg - r.R) / np.linalg.norm(r.R)
+    assert rerr <= tol * kappa, (rerr, tol * kappa)
+    qerr = np.linalg.norm(Qg - r.Q) / math.sqrt(n)
+    assert qerr <= tol * kappa, (qerr, tol * kappa)
+    return {"loo_gpu": loo_g, "loo_oracle": O.loss_of_orthogonality(r.Q),
+            "res": res, "r_err": rerr, "q_err": qerr}

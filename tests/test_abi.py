@@ -110,3 +110,56 @@ def test_status_strings():
     L = bcgs.lib()
     assert L.bcgs_status_string(0) == b"ok"
     assert L.bcgs_status_string(2) == b"Cholesky breakdown"
+
+
+def _problem(m=100, n=8, s=4, ldx=100, ldq=100, ldr=8, variant=2, prec=0,
+             X=0x100000, Q=0x9000000, R=0x20000000, info=0x80000000):
+    return bcgs.Problem(X, Q, R, m, n, s, ldx, ldq, ldr, variant, prec, info)
+
+
+def test_problem_struct_layout():
+    assert ctypes.sizeof(bcgs.Problem) == 88
+    assert bcgs.Problem.d_info.offset == 80
+    assert ctypes.sizeof(bcgs.Tuning) == 8
+
+
+@pytest.mark.parametrize("bad", [
+    dict(s=3), dict(m=7), dict(ldx=99), dict(ldq=50), dict(ldr=7),
+    dict(variant=9), dict(prec=5), dict(X=0), dict(info=0),
+    dict(Q=0x100000 + 800),             # Q overlaps X
+])
+def test_batched_rejects_any_bad_problem_synchronously(bad):
+    """One bad problem among good ones: BCGS_ERR_ARG before any device
+    call (the good problems use fake pointers that are never touched)."""
+    L = bcgs.lib()
+    good = _problem(X=0x200000, Q=0x300000, R=0x400000, info=0x500000)
+    arr = (bcgs.Problem * 2)(good, _problem(**bad))
+    assert L.bcgs_qr_batched(ctypes.byref(arr), 2, None) == bcgs.BCGS_ERR_ARG
+    assert L.bcgs_autotune(ctypes.byref(arr), 2, None) == bcgs.BCGS_ERR_ARG
+
+
+def test_batched_count_checks():
+    L = bcgs.lib()
+    assert L.bcgs_qr_batched(None, -1, None) == bcgs.BCGS_ERR_ARG
+    assert L.bcgs_qr_batched(None, 3, None) == bcgs.BCGS_ERR_ARG
+    assert L.bcgs_qr_batched(None, 0, None) == bcgs.BCGS_OK
+
+
+def test_tuning_table():
+    bcgs.tuning_clear()
+    assert bcgs.tuning_get(100000, 256, 16, "p-1s") == (512, -1, False)
+    bcgs.tuning_set(100000, 256, 16, "p-1s", max_wg=64, shape=2)
+    # the class is floor(log2 m): 65536 <= m < 131072
+    assert bcgs.tuning_get(70000, 256, 16, "p-1s") == (64, 2, True)
+    assert bcgs.tuning_get(131072, 256, 16, "p-1s")[2] is False
+    assert bcgs.tuning_get(100000, 256, 16, "p-2s")[2] is False
+    assert bcgs.tuning_get(100000, 256, 16, "p-1s", "fp32-bulk")[2] is False
+    with pytest.raises(bcgs.BcgsError):
+        bcgs.tuning_set(100000, 256, 16, "p-1s", max_wg=0)
+    with pytest.raises(bcgs.BcgsError):
+        bcgs.tuning_set(100000, 256, 16, "p-1s", max_wg=64, shape=99)
+    bcgs.tuning_set(100000, 256, 16, "p-1s")          # erase
+    assert bcgs.tuning_get(100000, 256, 16, "p-1s")[2] is False
+    bcgs.tuning_set(100000, 256, 16, "p-1s", max_wg=32)
+    bcgs.tuning_clear()
+    assert bcgs.tuning_get(100000, 256, 16, "p-1s")[2] is False
