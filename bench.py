@@ -20,6 +20,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
 FP64_PEAK_TFS = 78.6           # MI355X FP64 (vector and matrix), TFLOP/s
 METRIC = ("BCGSI+P-1S GB/s & %HBM peak vs BCGSI+, m=4M n=256 fp64; "
@@ -108,16 +110,21 @@ def kernel_name(kind, tag):
         # partial-sum areas, tile rows, Gram pairs per wave, B blocks
         nw, pc = (tag // 100000000) % 10, (tag // 10000000) % 10
         nbuf, scr2 = (tag // 1000000) % 10, (tag // 100000) % 10
+        reg = nbuf >= 5                  # tiles staged through registers
+        nbuf -= 5 if reg else 0
         tr, maxp, ntb = (tag // 1000) % 100, (tag // 10) % 100, tag % 10
         cap = {(64, 4): 64, (64, 8): 128, (32, 4): 128, (32, 8): 272,
-               (16, 4): 272, (16, 8): 272}.get((tr, nw), 0)
+               (16, 4): 272, (16, 8): 544}.get((tr, nw), 0)
+        if (tr, nw, nbuf) == (16, 4, 4):
+            cap = 272
         gram = "true" if ntb else "false"
+        r = "true" if reg else "false"
         if pc == 2:
             return (f"pass16_kernel<{tr}, {nbuf}, {cap}, {maxp}, {gram}, "
-                    f"{max(ntb, 1)}>")
+                    f"{max(ntb, 1)}, {r}>")
         return (f"pass16_deep_kernel<{tr}, {nbuf}, {cap}, {nw}, "
                 f"{'true' if scr2 else 'false'}, {maxp}, {gram}, "
-                f"{max(ntb, 1)}>")
+                f"{max(ntb, 1)}, {r}>")
     if kind == "pass":
         t = "float" if tag >= 1000 else "double"
         gram, ntb, maxa = (tag // 100) % 10, (tag // 10) % 10, tag % 10
@@ -226,6 +233,153 @@ def cpu_baseline(Xd, s, rows, model_bytes_full, m_full):
             "breakdown": None if r.breakdown is None else r.breakdown.block}
 
 
+def bench_batched(count, reps):
+    """The batched workload (uneven problems, P-1S, FP64): autotune, then
+    time `reps` rounds of one graph launch against the same problems
+    launched one after another on one stream."""
+    import torch
+    from paper_2507_21791_amd import bcgs, workloads as W
+    specs = W.batched_specs(count)
+    log(f"[bench] batched: generating {count} problems")
+    Xs = [W.conditioned_device(p["m"], p["n"], p["decades"], p["seed"])
+          for p in specs]
+    torch.cuda.synchronize()
+    items = [(X, p["s"], "p-1s", "fp64") for X, p in zip(Xs, specs)]
+    batch = bcgs.Batch(items)
+    t0 = time.perf_counter()
+    bcgs.autotune(batch)
+    tune_s = time.perf_counter() - t0
+    log(f"[bench] batched: autotune {tune_s:.2f} s")
+    stream = torch.cuda.current_stream()
+    wss = [bcgs.Workspace(p["m"], p["n"], p["s"], "p-1s") for p in specs]
+    outs = [(Q, R) for (_, Q, R, *_r) in batch.items]
+
+    def one_by_one():
+        for (X, s, v, pr), ws, (Q, R) in zip(items, wss, outs):
+            bcgs.qr(X, s, v, pr, Q=Q, R=R, ws=ws)
+
+    # algorithmic bytes of the whole batch, from the launch records
+    one_by_one()
+    torch.cuda.synchronize()
+    bcgs.profile_start(stream)
+    one_by_one()
+    model_bytes = sum(r["bytes"] for r in bcgs.profile_stop(stream))
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(reps):
+        one_by_one()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_single = e0.elapsed_time(e1) / reps
+    bcgs.qr_batched(batch)          # capture + first replay
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(reps):
+        bcgs.qr_batched(batch)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_batch = e0.elapsed_time(e1) / reps
+    res = batch.results()
+    breakdowns = sum(1 for _, _, info in res if info.status != 0)
+    out = {"workload": (f"{count} problems, m U[10000,200000], n in "
+                        "{32,64,128,256}, s in {8,16}, kappa 1e2..1e10, "
+                        "P-1S FP64"),
+           "ms_batched": round(ms_batch, 3),
+           "ms_one_by_one": round(ms_single, 3),
+           "speedup": round(ms_single / ms_batch, 3),
+           "problems_per_s": round(count / (ms_batch * 1e-3), 1),
+           "model_gb": round(model_bytes / 1e9, 3),
+           "gbs": round(model_bytes / (ms_batch * 1e-3) / 1e9, 1),
+           "autotune_s": round(tune_s, 2),
+           "breakdowns": breakdowns}
+    log(f"[bench] batched: {out}")
+    del Xs, batch, wss, outs
+    torch.cuda.empty_cache()
+    return out
+
+
+def bench_served(nreq, rate, precision, pool, pool32, loo_every=50,
+                 inflight=8, budget=96 << 30, arena=64 << 30):
+    """Poisson arrivals at `rate` req/s of P-1S requests drawn from the
+    device pool, through the library's request queue (continuous batching,
+    queue-allocated outputs).  Latency = completion - submission (the
+    submitter submits at each arrival time)."""
+    import threading
+    import torch
+    from paper_2507_21791_amd import bcgs, workloads as W
+    trace = W.served_trace(nreq, rate, len(pool))
+    src = pool if precision == "fp64" else pool32
+    q = bcgs.Queue(hbm_budget_bytes=budget, max_inflight=inflight,
+                   output_arena_bytes=arena)
+    tickets = [None] * nreq
+    sampled = {}
+
+    def submitter():
+        t0 = time.perf_counter()
+        for i, (arr, k) in enumerate(trace):
+            d = arr - (time.perf_counter() - t0)
+            if d > 0:
+                time.sleep(d)
+            caller = (i % loo_every) == 0
+            tickets[i] = q.submit(src[k][0], 16, "p-1s", precision,
+                                  outputs="caller" if caller else "queue")
+            if caller:
+                sampled[i] = k
+
+    th = threading.Thread(target=submitter)
+    th.start()
+    res = [None] * nreq
+    for i in range(nreq):
+        while tickets[i] is None:
+            time.sleep(0.0002)
+        r = q.wait(tickets[i])
+        if r["Q_ptr"]:
+            q.free(r["Q_ptr"])
+            q.free(r["R_ptr"])
+        res[i] = r
+    th.join()
+    q.close()
+    lat = np.array([r["t_done"] - r["t_submit"] for r in res]) * 1e3
+    span = max(r["t_done"] for r in res) - min(r["t_submit"] for r in res)
+    loos = []
+    for i, k in sampled.items():
+        r = res[i]
+        if r["status"] == 0:
+            X = src[k][0].double() if precision != "fp64" else src[k][0]
+            loo, resid = accuracy(X, r["Q"].double(), r["R"])
+            loos.append((loo, resid))
+    out = {"rate_per_s": rate, "requests": nreq, "precision": precision,
+           "p50_ms": round(float(np.percentile(lat, 50)), 3),
+           "p99_ms": round(float(np.percentile(lat, 99)), 3),
+           "throughput_per_s": round(nreq / span, 1),
+           "breakdowns": int(sum(1 for r in res if r["status"] == 2)),
+           "errors": int(sum(1 for r in res if r["status"] not in (0, 2))),
+           "sampled_loo_max": max((l for l, _ in loos), default=None),
+           "sampled_residual_max": max((r for _, r in loos), default=None),
+           "sampled": len(loos)}
+    log(f"[bench] served: {out}")
+    return out
+
+
+def served_pool(count):
+    import torch
+    from paper_2507_21791_amd import workloads as W
+    specs = W.served_pool_specs(count)
+    log(f"[bench] served: generating a pool of {count} inputs")
+    pool, pool32 = [], []
+    for p in specs:
+        X = W.conditioned_device(p["m"], p["n"], p["decades"], p["seed"])
+        pool.append((X, p))
+        X32 = torch.empty((p["n"], p["m"]), dtype=torch.float32,
+                          device="cuda").t()
+        X32.copy_(X)
+        pool32.append((X32, p))
+    torch.cuda.synchronize()
+    return pool, pool32
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -238,6 +392,11 @@ def main():
     ap.add_argument("--cpu-rows", type=int, default=1 << 20)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-check", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--batched-count", type=int, default=256)
+    ap.add_argument("--no-served", action="store_true")
+    ap.add_argument("--served-n", type=int, default=1000)
+    ap.add_argument("--served-pool", type=int, default=24)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (counter "
                          "calibration for rocprofv3 --pmc runs)")
@@ -326,10 +485,31 @@ def main():
     out["variants"] = {k: {kk: vv for kk, vv in r.items() if kk != "_agg"}
                        for k, r in results.items()}
     out["p99_latency_ms"] = None
+    rows = min(args.cpu_rows, m)
+    Xhead = None if args.no_cpu else X[:rows].cpu()
+    del X, Q, R
+    torch.cuda.empty_cache()
+    if not args.no_batched:
+        out["batched"] = bench_batched(args.batched_count, 3)
+    if not args.no_served:
+        pool, pool32 = served_pool(args.served_pool)
+        served = [bench_served(args.served_n, 2000.0, "fp64", pool, pool32),
+                  bench_served(max(1, args.served_n // 3), 300.0, "fp64",
+                               pool, pool32),
+                  bench_served(args.served_n, 2000.0, "fp32-bulk", pool,
+                               pool32)]
+        out["served"] = {
+            "workload": (f"Poisson arrivals, P-1S, s=16, pool of "
+                         f"{args.served_pool} device-resident inputs (m "
+                         "log-uniform 4096..2^21, n 16..512, kappa "
+                         "1e2..1e8) drawn with replacement"),
+            "runs": served}
+        out["p99_latency_ms"] = served[0]["p99_ms"]
+        del pool, pool32
+        torch.cuda.empty_cache()
     if not args.no_cpu:
-        rows = min(args.cpu_rows, m)
         log(f"[bench] cpu baseline: oracle on {rows} rows")
-        out["cpu_baseline"] = cpu_baseline(X, s, rows,
+        out["cpu_baseline"] = cpu_baseline(Xhead, s, rows,
                                            head["model_gb"] * 1e9, m)
     print(json.dumps(out), flush=True)
 

@@ -200,6 +200,81 @@ bcgs_status bcgs_tuning_set(int64_t m, int64_t n, int64_t s,
 /* Erase every entry. */
 void bcgs_tuning_clear(void);
 
+/* ---- request queue with continuous batching -------------------------------
+ * For serving: callers on any thread submit requests without blocking; one
+ * scheduler thread per queue admits them in arrival order onto up to
+ * max_inflight library streams whenever a stream is free and the request's
+ * HBM footprint (X + Q + R + its workspace) fits in the budget left by the
+ * running requests (a request is always admitted when nothing runs, so one
+ * larger than the budget still completes).  Requests admitted while others
+ * run overlap with them on the device.  Each request runs exactly the
+ * computation bcgs_qr_ex would run for it (same kernels, same tuned
+ * choices), so its results are bitwise the same alone and in the mix. */
+typedef struct bcgs_queue* bcgs_queue_t;
+
+typedef struct {
+    size_t hbm_budget_bytes;    /* > 0 */
+    int32_t max_inflight;       /* 1..16 concurrently running requests */
+    int32_t device;             /* HIP device ordinal */
+    size_t output_arena_bytes;  /* device memory for queue-allocated Q and
+                                   R (0: every request brings its own) */
+} bcgs_queue_config;
+
+/* Outcome of one request; times are seconds on the host's steady clock
+ * since the queue was created: submitted, admitted (work enqueued), and
+ * found complete by the scheduler (which polls every ~20 us).  Q and R are
+ * the queue-allocated outputs (ld = m and n), else NULL. */
+typedef struct {
+    bcgs_status status;       /* BCGS_PENDING, BCGS_OK, BCGS_ERR_BREAKDOWN,
+                                 or the error that stopped the request */
+    bcgs_info info;           /* copy of the request's device record */
+    double t_submit, t_start, t_done;
+    void* Q;
+    double* R;
+} bcgs_request_stats;
+
+/* Create a queue (library streams, pinned info buffers, the output arena,
+ * scheduler thread).  BCGS_ERR_ARG on a bad configuration, BCGS_ERR_NOMEM
+ * if the arena cannot be allocated, BCGS_ERR_HIP on runtime failure. */
+bcgs_status bcgs_queue_create(const bcgs_queue_config* cfg,
+                              bcgs_queue_t* out);
+
+/* Submit one problem (host struct; device buffers stay owned by the caller
+ * and must stay valid until the request completes).  With p->Q and p->R
+ * both NULL the queue carves them out of its output arena at admission
+ * (ld = m and n; admission waits, in arrival order, until the arena has
+ * room) and returns them in the stats; the caller returns them with
+ * bcgs_queue_free_output.  Never waits for the device.
+ * BCGS_ERR_ARG (the checks of bcgs_qr_ex, queue-allocated outputs without
+ * an arena, or the queue is being destroyed), BCGS_ERR_NOMEM (the outputs
+ * can never fit the arena), BCGS_ERR_QUEUE_FULL (2^20 requests waiting),
+ * BCGS_ERR_HIP (an earlier request hit a runtime failure), else BCGS_OK
+ * and *ticket. */
+bcgs_status bcgs_queue_submit(bcgs_queue_t q, const bcgs_problem* p,
+                              uint64_t* ticket);
+
+/* Non-blocking: BCGS_PENDING (stats so far), or the final status with the
+ * final stats, after which the ticket is forgotten (BCGS_ERR_ARG on an
+ * unknown or already collected ticket). */
+bcgs_status bcgs_queue_poll(bcgs_queue_t q, uint64_t ticket,
+                            bcgs_request_stats* out);
+
+/* Block until the request has finished; then as bcgs_queue_poll. */
+bcgs_status bcgs_queue_wait(bcgs_queue_t q, uint64_t ticket,
+                            bcgs_request_stats* out);
+
+/* Return a queue-allocated Q or R to the arena once the work enqueued on
+ * `stream` so far has finished (an event recorded there).  NULL is a
+ * no-op; BCGS_ERR_ARG for a pointer the arena did not hand out. */
+bcgs_status bcgs_queue_free_output(bcgs_queue_t q, void* ptr,
+                                   hipStream_t stream);
+
+/* Run every submitted request to completion (a request still waiting for
+ * arena space that nothing will free finishes with BCGS_ERR_NOMEM), then
+ * free the queue and its arena.  No other call on the queue may be in
+ * progress or follow. */
+bcgs_status bcgs_queue_destroy(bcgs_queue_t q);
+
 /* ---- launch profiling ----------------------------------------------------
  * Between bcgs_profile_start(stream) and bcgs_profile_stop(stream, ...), every
  * kernel the library enqueues on `stream` is bracketed by HIP events and

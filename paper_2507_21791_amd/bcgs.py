@@ -61,6 +61,21 @@ class Tuning(ctypes.Structure):
     _fields_ = [("max_wg", ctypes.c_int32), ("shape", ctypes.c_int32)]
 
 
+class QueueConfig(ctypes.Structure):
+    """Mirror of bcgs_queue_config."""
+    _fields_ = [("hbm_budget_bytes", ctypes.c_size_t),
+                ("max_inflight", ctypes.c_int32), ("device", ctypes.c_int32),
+                ("output_arena_bytes", ctypes.c_size_t)]
+
+
+class RequestStats(ctypes.Structure):
+    """Mirror of bcgs_request_stats."""
+    _fields_ = [("status", ctypes.c_int), ("info", Info),
+                ("t_submit", ctypes.c_double), ("t_start", ctypes.c_double),
+                ("t_done", ctypes.c_double), ("Q", ctypes.c_void_p),
+                ("R", ctypes.c_void_p)]
+
+
 _lib = None
 
 _PROTOS = {
@@ -94,6 +109,17 @@ _PROTOS = {
                                        ctypes.c_int64, ctypes.c_int,
                                        ctypes.c_int, ctypes.c_void_p]),
     "bcgs_tuning_clear": (None, []),
+    "bcgs_queue_create": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "bcgs_queue_submit": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p,
+                                         ctypes.c_void_p]),
+    "bcgs_queue_poll": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64,
+                                       ctypes.c_void_p]),
+    "bcgs_queue_wait": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64,
+                                       ctypes.c_void_p]),
+    "bcgs_queue_destroy": (ctypes.c_int, [ctypes.c_void_p]),
+    "bcgs_queue_free_output": (ctypes.c_int, [ctypes.c_void_p,
+                                              ctypes.c_void_p,
+                                              ctypes.c_void_p]),
     "bcgs_profile_start": (ctypes.c_int, [ctypes.c_void_p]),
     "bcgs_profile_stop": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p,
                                            ctypes.c_int32]),
@@ -315,3 +341,96 @@ def tuning_set(m, n, s, variant, precision="fp64", max_wg=None, shape=-1):
 
 def tuning_clear():
     lib().bcgs_tuning_clear()
+
+
+BCGS_PENDING = 6
+
+
+class Queue:
+    """Request queue with continuous batching (bcgs_queue_*).  Holds the
+    tensors of every request until it is collected."""
+
+    def __init__(self, hbm_budget_bytes, max_inflight=8, device=0,
+                 output_arena_bytes=0):
+        self.handle = ctypes.c_void_p()
+        cfg = QueueConfig(int(hbm_budget_bytes), int(max_inflight),
+                          int(device), int(output_arena_bytes))
+        st = lib().bcgs_queue_create(ctypes.byref(cfg),
+                                     ctypes.byref(self.handle))
+        if st != BCGS_OK:
+            raise BcgsError(st, "bcgs_queue_create")
+        self.live = {}
+
+    def submit(self, X, s, variant="p-1s", precision="fp64", Q=None, R=None,
+               outputs="caller"):
+        """Submit X = QR; returns the ticket.  outputs="caller": Q and R are
+        torch tensors (allocated here when not given); outputs="queue": the
+        queue carves them out of its output arena at admission and the
+        result carries their device pointers (return them with free()).  The tensors and a device
+        info record stay alive until the request is collected."""
+        import torch
+        m, n = X.shape
+        ldx = _col_major(X, "X")
+        want = torch.float64 if precision == "fp64" else torch.float32
+        if X.dtype != want:
+            raise ValueError(f"X must be {want} for precision {precision}")
+        if outputs == "queue":
+            Q = R = None
+            qp = rp = None
+            ldq, ldr = m, n
+        else:
+            if Q is None:
+                Q = empty_fortran(m, n, want, X.device)
+            if R is None:
+                R = empty_fortran(n, n, torch.float64, X.device)
+            qp, rp = Q.data_ptr(), R.data_ptr()
+            ldq, ldr = _col_major(Q, "Q"), _col_major(R, "R")
+        # no kernel here: the request's own first kernel initializes the
+        # record, on the queue's stream
+        info = torch.empty(INFO_BYTES, dtype=torch.uint8, device=X.device)
+        prob = Problem(X.data_ptr(), qp, rp, m, n, s, ldx, ldq, ldr,
+                       VARIANTS[variant], PRECISIONS[precision],
+                       info.data_ptr())
+        t = ctypes.c_uint64()
+        st = lib().bcgs_queue_submit(self.handle, ctypes.byref(prob),
+                                     ctypes.byref(t))
+        if st != BCGS_OK:
+            raise BcgsError(st, "bcgs_queue_submit")
+        self.live[t.value] = (X, Q, R, info)
+        return t.value
+
+    def _finish(self, fn, ticket):
+        out = RequestStats()
+        st = fn(self.handle, ticket, ctypes.byref(out))
+        if st == BCGS_PENDING:
+            return None
+        if st == BCGS_ERR_ARG and ticket not in self.live:
+            raise BcgsError(st, "unknown ticket")
+        X, Q, R, info = self.live.pop(ticket)
+        return {"status": st, "info": out.info, "t_submit": out.t_submit,
+                "t_start": out.t_start, "t_done": out.t_done, "Q": Q, "R": R,
+                "Q_ptr": out.Q, "R_ptr": out.R}
+
+    def free(self, ptr, stream=None):
+        """Return a queue-allocated Q or R to the arena once the work on
+        `stream` (the current stream by default) so far has finished."""
+        if ptr:
+            st = lib().bcgs_queue_free_output(self.handle, ctypes.c_void_p(ptr),
+                                              _stream_handle(stream))
+            if st != BCGS_OK:
+                raise BcgsError(st, "bcgs_queue_free_output")
+
+    def poll(self, ticket):
+        """None while pending, else a dict (status, info, times, Q, R)."""
+        return self._finish(lib().bcgs_queue_poll, ticket)
+
+    def wait(self, ticket):
+        return self._finish(lib().bcgs_queue_wait, ticket)
+
+    def close(self):
+        if self.handle:
+            st = lib().bcgs_queue_destroy(self.handle)
+            self.handle = ctypes.c_void_p()
+            self.live.clear()
+            if st != BCGS_OK:
+                raise BcgsError(st, "bcgs_queue_destroy")

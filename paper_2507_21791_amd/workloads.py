@@ -177,3 +177,48 @@ def hadamard_columns(m, n, exponents):
         H = np.block([[H, H], [H, -H]])
     X = H[:, :n] * np.ldexp(1.0, np.asarray(exponents, dtype=int))[None, :]
     return np.asfortranarray(X)
+
+
+# ------------------------------------------------ batched and served mixes ---
+
+
+def batched_specs(count=256, seed=4):
+    """Shapes of the batched workload: `count` independent problems with m
+    uniform in [10000, 200000], n in {32, 64, 128, 256}, s in {8, 16} and
+    singular values logspace(0, -c, n), c uniform in [2, 10].  Returns a
+    list of dicts (m, n, s, decades, seed); problem i is generated from
+    seed + i."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(count):
+        out.append(dict(m=int(rng.integers(10000, 200001)),
+                        n=int(rng.choice([32, 64, 128, 256])),
+                        s=int(rng.choice([8, 16])),
+                        decades=float(rng.uniform(2.0, 10.0)),
+                        seed=seed + i))
+    return out
+
+
+def served_pool_specs(count, seed=5):
+    """Inputs of the served stream, drawn once into a device pool: m
+    log-uniform in [4096, 2^21], n in {16, 32, ..., 512}, s = 16 and
+    kappa log-uniform in [1e2, 1e8] (singular values logspace(0, -c, n))."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(count):
+        m = int(round(math.exp(rng.uniform(math.log(4096),
+                                           math.log(1 << 21)))))
+        n = int(16 * rng.integers(1, 33))
+        out.append(dict(m=max(m, n), n=n, s=16,
+                        decades=float(rng.uniform(2.0, 8.0)),
+                        seed=1000 * seed + i))
+    return out
+
+
+def served_trace(nreq, rate, pool_size, seed=5):
+    """Poisson arrivals at `rate` requests/s: (arrival time in s, pool index
+    drawn uniformly with replacement) for each of `nreq` requests."""
+    rng = np.random.default_rng(seed + 7919)
+    t = np.cumsum(rng.exponential(1.0 / rate, size=nreq))
+    idx = rng.integers(0, pool_size, size=nreq)
+    return [(float(a), int(b)) for a, b in zip(t, idx)]

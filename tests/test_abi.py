@@ -163,3 +163,36 @@ def test_tuning_table():
     bcgs.tuning_set(100000, 256, 16, "p-1s", max_wg=32)
     bcgs.tuning_clear()
     assert bcgs.tuning_get(100000, 256, 16, "p-1s")[2] is False
+
+
+def test_queue_struct_layouts():
+    assert ctypes.sizeof(bcgs.QueueConfig) == 24
+    assert bcgs.QueueConfig.output_arena_bytes.offset == 16
+    assert ctypes.sizeof(bcgs.RequestStats) == 80
+    assert bcgs.RequestStats.info.offset == 8
+    assert bcgs.RequestStats.t_done.offset == 56
+    assert bcgs.RequestStats.R.offset == 72
+
+
+@pytest.mark.parametrize("budget,inflight", [(0, 4), (1 << 30, 0),
+                                             (1 << 30, 17)])
+def test_queue_bad_config_rejected(budget, inflight):
+    L = bcgs.lib()
+    cfg = bcgs.QueueConfig(budget, inflight, 0)
+    h = ctypes.c_void_p()
+    assert L.bcgs_queue_create(ctypes.byref(cfg), ctypes.byref(h)) == \
+        bcgs.BCGS_ERR_ARG
+    assert L.bcgs_queue_create(None, ctypes.byref(h)) == bcgs.BCGS_ERR_ARG
+
+
+def test_queue_null_handles_rejected():
+    L = bcgs.lib()
+    p = _problem()
+    t = ctypes.c_uint64()
+    out = bcgs.RequestStats()
+    assert L.bcgs_queue_submit(None, ctypes.byref(p), ctypes.byref(t)) == \
+        bcgs.BCGS_ERR_ARG
+    assert L.bcgs_queue_poll(None, 1, ctypes.byref(out)) == bcgs.BCGS_ERR_ARG
+    assert L.bcgs_queue_wait(None, 1, ctypes.byref(out)) == bcgs.BCGS_ERR_ARG
+    assert L.bcgs_queue_destroy(None) == bcgs.BCGS_ERR_ARG
+    assert L.bcgs_queue_free_output(None, FAKE, None) == bcgs.BCGS_ERR_ARG

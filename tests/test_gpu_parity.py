@@ -10,7 +10,7 @@ import pytest
 import oracle as O
 from paper_2507_21791_amd import workloads as W
 
-from parity import compare, host, log, run_gpu
+from parity import compare, host, log, run_gpu, to_device
 
 pytestmark = pytest.mark.gpu
 VARIANTS = ["bcgsi+", "p-2s", "p-1s"]
@@ -42,7 +42,8 @@ SHAPES = [  # (m, n, s, decades)
     (1000, 64, 16, 4), (257, 48, 1, 2), (257, 48, 2, 3), (257, 48, 3, 3),
     (513, 60, 5, 3), (40, 40, 8, 1), (2000, 128, 32, 3), (3000, 128, 64, 3),
     (4099, 96, 16, 5), (10000, 24, 8, 2), (777, 16, 16, 3), (777, 32, 16, 3),
-    (33000, 48, 16, 4),
+    (33000, 48, 16, 4), (20001, 512, 16, 3), (16384, 400, 16, 3),
+    (100001, 256, 16, 4), (50001, 160, 8, 3),
 ]
 
 
@@ -156,3 +157,25 @@ def test_library_owned_workspace_entry_point():
     info = bcgs.get_info()
     assert info.status == 0 and info.syncs == 9
     compare(X, 8, "p-1s", host(Q), host(R), info, kappa=1e4)
+
+
+@pytest.mark.parametrize("m,n", [(40001, 128), (40000, 512), (30001, 480)])
+def test_fast_pass_takes_odd_rows_and_wide_blocks(m, n):
+    """Odd leading dimensions run the register-staged form of the s <= 16
+    pass and n up to 512 the 544-column shape (not the general pass); the
+    result meets the oracle's tolerances."""
+    import torch
+    from paper_2507_21791_amd import bcgs
+    log(f"[gpu] s=16 fast pass m={m} n={n}")
+    X = W.conditioned_host(m, n, 3, seed=m + n)
+    Xd = to_device(X, torch.float64)
+    ws = bcgs.Workspace(m, n, 16, "p-1s")
+    stream = torch.cuda.current_stream()
+    bcgs.profile_start(stream)
+    Q, R, _ = bcgs.qr(Xd, 16, "p-1s", ws=ws)
+    recs = bcgs.profile_stop(stream)
+    tags = [r["tag"] for r in recs if r["kind"] == "pass"]
+    assert tags and all(t >= 10 ** 9 for t in tags), tags
+    if m % 2:
+        assert all((t // 10 ** 6) % 10 >= 5 for t in tags), tags
+    compare(X, 16, "p-1s", host(Q), host(R), ws.info(), kappa=1e3)
