@@ -148,7 +148,7 @@ def measured_traffic(kernel):
         lines = open(path).read().splitlines()
     except OSError:
         return None
-    digest = [l.split(":")[1].strip() for l in lines
+    digest = [l.split(":")[1].split()[0] for l in lines
               if l.startswith("# kernel sources digest:")]
     if not digest or digest[0] != source_digest(root):
         return None

@@ -30,6 +30,7 @@ def short_name(name):
     n = re.sub(r"\(.*", "", name)
     n = n.replace("void ", "").replace("bcgs::", "")
     n = n.replace("p16::", "").replace("tq::", "tsqr_")
+    n = n.replace("tw::", "tsqr_wave_")
     return n.strip()
 
 
@@ -37,15 +38,21 @@ def ours(name):
     return "bcgs::" in name
 
 
+# sources of the dominant kernel (the s <= 16 streaming pass)
+PASS_SOURCES = ("pass16_impl.h", "pass16.hip", "pass16_reg.hip", "common.h")
+
+
 def source_digest(root):
-    """sha256 over the kernel sources, to tell whether counters are stale."""
+    """sha256 over the sources of the s <= 16 pass kernels, to tell whether
+    their counters are stale."""
     h = hashlib.sha256()
     cdir = os.path.join(root, "paper_2507_21791_amd", "csrc")
-    for f in sorted(os.listdir(cdir)):
-        if f.endswith((".hip", ".h")):
-            with open(os.path.join(cdir, f), "rb") as fh:
-                h.update(f.encode())
-                h.update(fh.read())
+    for f in PASS_SOURCES:
+        with open(os.path.join(cdir, f), "rb") as fh:
+            h.update(f.encode())
+            h.update(fh.read())
+    with open(os.path.join(root, "include", "bcgs.h"), "rb") as fh:
+        h.update(fh.read())
     return h.hexdigest()[:16]
 
 
@@ -112,7 +119,7 @@ def counters(dfetch, dwrite, prefix, cmd, root):
     out = ["# rocprofv3 HBM traffic summary (FETCH_SIZE run, then WRITE_SIZE "
            "run)", f"# command (twice, --pmc FETCH_SIZE / --pmc WRITE_SIZE): "
            f"{cmd}",
-           f"# kernel sources digest: {source_digest(root)}",
+           f"# kernel sources digest: {source_digest(root)} (s <= 16 pass sources)",
            "# calibration: 1 GiB plain device copy reads "
            f"{GIB_KIB / cal['FETCH_SIZE']:.0f} KiB FETCH_SIZE and "
            f"{GIB_KIB / cal['WRITE_SIZE']:.0f} KiB WRITE_SIZE;",
