@@ -22,9 +22,12 @@ namespace bcgs {
 struct EpiSmem {
   double A[kMaxS * kMaxS];     // matrix being factored (row-major s x s)
   double B[kMaxS * kMaxS];     // scratch s x s
+  double P[256];               // 16 x 16 right operand of mm16
   double bc[4];
   int flag;
 };
+
+typedef double v4d __attribute__((ext_vector_type(4)));
 
 // Upper Cholesky of the s x s matrix in sm.A (row-major, symmetric); the
 // factor overwrites sm.A's upper triangle and the lower part is zeroed.
@@ -153,6 +156,106 @@ __device__ __forceinline__ double gram_at(const EpiArgs& a, int r, int c) {
   return a.gram[(size_t)c * a.gld + r];
 }
 
+// Tall-by-small products on the FP64 16x16x4 MFMA, for block widths
+// S = 4, 8, 16: out(i, c, v) receives v = sum_{k < S} A(i, k) P(k, c) for
+// i < rows and c < 16, with P a 16 x 16 row-major LDS matrix that is zero
+// outside its S x S corner (so columns c >= S come out zero).  Row blocks
+// of 16 go round-robin to the waves; a_at(i, k) is called only for
+// i < rows, k < S.  Operand layout: A[l % 16][l / 16], B[l / 16][l % 16],
+// result v at lane l: row l / 16 + 4 v, column l % 16.
+template <int S, class FA, class FO>
+__device__ __forceinline__ void mm16(int rows, FA a_at, const double* P,
+                                     FO out) {
+  static_assert(S == 4 || S == 8 || S == 16, "16x16x4 blocks");
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  for (int rb = wave; rb * 16 < rows; rb += kWaves) {
+    const int i = rb * 16 + li;
+    double av[S / 4];
+#pragma unroll
+    for (int q = 0; q < S / 4; ++q)
+      av[q] = i < rows ? a_at(i, 4 * q + lk) : 0.0;
+    v4d acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int q = 0; q < S / 4; ++q)
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[q], P[(4 * q + lk) * 16 + li],
+                                                 acc, 0, 0, 0);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int r = rb * 16 + lk + 4 * v;
+      if (r < rows) out(r, li, acc[v]);
+    }
+  }
+}
+
+// P <- the S x S row-major matrix M (leading dimension ldm), zero-padded
+// to 16 x 16
+template <int S>
+__device__ __forceinline__ void load_p(EpiSmem& sm, const double* M,
+                                       int ldm) {
+  for (int e = threadIdx.x; e < 256; e += kThreads) {
+    const int k = e >> 4, c = e & 15;
+    sm.P[e] = (k < S && c < S) ? M[k * ldm + c] : 0.0;
+  }
+}
+
+// W^T W over the js rows of W = Gram columns [0, w) (w = 2S with the E
+// block, else S), split into the S x S blocks Y^T Y, Y^T Z, Z^T Z of
+// W = [Y Z]: one 16x16x4 MFMA chain per 16 x 16 block, the rows dealt to
+// the waves in 4-row steps, the four wave partials summed in a fixed order
+// in LDS (scr: 4 x 3 x 256 doubles).  Thread e < S*S receives entry
+// (e / S, e % S) of each block.
+template <int S>
+__device__ void gram_products(const EpiArgs& a, int js, bool has_e,
+                              double* scr, double& yy, double& yz,
+                              double& zz) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int w = has_e ? 2 * S : S;
+  v4d b00 = {0.0, 0.0, 0.0, 0.0}, b01 = b00, b11 = b00;
+  const int nsteps = (js + 3) / 4;
+  // column li of the first 16-column block; for S = 16 also of the second
+  const int c0 = li, c1 = 16 + li;
+  for (int t = wave; t < nsteps; t += kWaves) {
+    const int r = 4 * t + lk;
+    const double x0 = (r < js && c0 < w) ? gram_at(a, r, c0) : 0.0;
+    b00 = __builtin_amdgcn_mfma_f64_16x16x4f64(x0, x0, b00, 0, 0, 0);
+    if (S == 16 && has_e) {
+      const double x1 = r < js ? gram_at(a, r, c1) : 0.0;
+      b01 = __builtin_amdgcn_mfma_f64_16x16x4f64(x0, x1, b01, 0, 0, 0);
+      b11 = __builtin_amdgcn_mfma_f64_16x16x4f64(x1, x1, b11, 0, 0, 0);
+    }
+  }
+  double* mine = scr + wave * 3 * 256;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int e = (lk + 4 * v) * 16 + li;
+    mine[e] = b00[v];
+    mine[256 + e] = b01[v];
+    mine[512 + e] = b11[v];
+  }
+  __syncthreads();
+  const int e = threadIdx.x;
+  if (e < S * S) {
+    const int x = e / S, y = e % S;
+    // block and offset of (x, y) in Y^T Y, (x, S + y) in Y^T Z and
+    // (S + x, S + y) in Z^T Z
+    auto sum = [&](int blk, int row, int col) {
+      double v = 0.0;
+#pragma unroll
+      for (int q = 0; q < kWaves; ++q)
+        v += scr[q * 3 * 256 + blk * 256 + row * 16 + col];
+      return v;
+    };
+    yy = sum(0, x, y);
+    if (has_e) {
+      yz = S == 16 ? sum(1, x, y) : sum(0, x, S + y);
+      zz = S == 16 ? sum(2, x, y) : sum(0, S + x, S + y);
+    }
+  }
+  __syncthreads();
+}
+
 __device__ void store_tri(double* dst, int sp, int s, const double* src) {
   for (int e = threadIdx.x; e < sp * sp; e += kThreads) {
     const int i = e / sp, l = e % sp;
@@ -174,6 +277,16 @@ __device__ void assemble_r(EpiSmem& sm, const EpiArgs& a, const double* c1,
   for (int e = threadIdx.x; e < s * s; e += kThreads)
     T2[e] = t2[(e / s) * sp + e % s];
   __syncthreads();
+  if constexpr (S == 4 || S == 8 || S == 16) {
+    load_p<S>(sm, T2, S);
+    __syncthreads();
+    mm16<S>(
+        js, [&](int i, int k) { return c1[(size_t)i * sp + k]; }, sm.P,
+        [&](int i, int c, double v) {
+          if (c < S)
+            a.r[(size_t)(js + c) * a.ldr + i] = v + c2[(size_t)i * sp + c];
+        });
+  } else
   for (int i = threadIdx.x; i < js; i += kThreads) {
     double y[S ? S : kMaxS];
 #pragma unroll
@@ -234,6 +347,14 @@ __device__ void make_coef(EpiSmem& sm, double* F, const double* C, int K,
       Ti[e] = (e / s == e % s) ? 1.0 : 0.0;
   }
   __syncthreads();
+  if constexpr (S == 4 || S == 8 || S == 16) {
+    // F(0:K, :) = -C T^{-1} (Ti is the identity when unscaled)
+    load_p<S>(sm, Ti, S);
+    __syncthreads();
+    mm16<S>(
+        K, [&](int i, int k) { return C[(size_t)i * sp + k]; }, sm.P,
+        [&](int i, int c, double v) { F[(size_t)i * sp + c] = -v; });
+  } else
   // one row of C per thread: F(i, :) = -C(i, :) T^{-1}  (or -C(i, :))
   for (int i = tid; i < K; i += kThreads) {
     double cr[S ? S : kMaxS];
@@ -276,6 +397,18 @@ template <int S>
 __device__ void fold_coefs(EpiSmem& sm, const EpiArgs& a) {
   const int s = S ? S : a.s, sp = a.sp, K1 = a.f1_rows;
   double* M = sm.A;                   // F2(K1 : K1+s), s x s row-major
+  if constexpr (S == 4 || S == 8 || S == 16) {
+    load_p<S>(sm, a.f2 + (size_t)K1 * sp, sp);
+    __syncthreads();
+    mm16<S>(
+        K1 + s, [&](int i, int k) { return a.f1[(size_t)i * sp + k]; },
+        sm.P, [&](int i, int c, double v) {
+          double* o = a.f2 + (size_t)i * sp + c;
+          *o = (i < K1 ? *o : 0.0) + v;
+        });
+    __syncthreads();
+    return;
+  }
   for (int e = threadIdx.x; e < s * s; e += kThreads)
     M[e] = a.f2[(size_t)(K1 + e / s) * sp + e % s];
   __syncthreads();
@@ -372,7 +505,9 @@ __device__ void epilogue_body(EpiArgs a, EpiSmem& sm) {
   double yy[kPer], yz[kPer], zz[kPer];
 #pragma unroll
   for (int t = 0; t < kPer; ++t) yy[t] = yz[t] = zz[t] = 0.0;
-  {
+  if constexpr (S == 4 || S == 8 || S == 16) {
+    gram_products<S>(a, js, a.has_e, sm.B, yy[0], yz[0], zz[0]);
+  } else {
     double* stg = sm.A;               // rows x w2, row-major
     const int crows = (kMaxS * kMaxS) / w2;
     for (int r0 = 0; r0 < js; r0 += crows) {
