@@ -66,6 +66,13 @@ class _Backend:
         raise NotImplementedError
 
     # -- plain algorithms --------------------------------------------
+    def eye(self, n):
+        """n x n identity in this number system."""
+        out = self.zeros((n, n))
+        for i in range(n):
+            out[i, i] = out[i, i] + 1
+        return out
+
     def matmul(self, A, B):
         return A @ B
 

@@ -23,6 +23,11 @@ Readings of passages the paper leaves implicit:
   * Alg. 2 is written for q >= 3.  For q = 1 only TSQR(X_1) runs; for q = 2
     the first product after U_2 is [Q_1 U_2]^T U_2, the form Alg. 2 itself
     uses in its last iteration.
+  * BCGSI+1s is described (section 2.2) as Alg. 2 without its first
+    intra-orthogonalization (the chol that forms S_{k+1,k+1}): U_{k+1} =
+    X_{k+1} - Q_{1:k} S is not scaled, i.e. S_{k+1,k+1} = I, so R_{1:k,k+1}
+    = S + Y and R_{k+1,k+1} = Y_{k+1,k+1}.  The same holds for the first
+    block (S_12 = Q_1^T X_2, U_2 = X_2 - Q_1 S_12), and T is never formed.
 """
 
 from dataclasses import dataclass, field
@@ -150,9 +155,10 @@ def _delayed_s(bk, Z_prev, P_k, Y_prev, Y_kk):
 
 
 def _one_or_two_sync(X, s, bk, stats, first_intra):
-    """Alg. 2 and its two-sync sibling, which differ only in the first
+    """Alg. 2 and its siblings, which differ only in the first
     intra-orthogonalization of each block column (``first_intra`` is
-    "chol" for BCGSI+P-1S, "tsqr" for BCGSI+P-2S, section 2.3)."""
+    "chol" for BCGSI+P-1S, "tsqr" for BCGSI+P-2S (section 2.3), "none" for
+    BCGSI+1s (section 2.2, S_{k+1,k+1} = I))."""
     m, n = X.shape
     q = n // s
     Q = bk.zeros((m, n))
@@ -172,11 +178,17 @@ def _one_or_two_sync(X, s, bk, stats, first_intra):
         S22 = _chol(bk, T2 - bk.matmul(S12.T, S12), 1, "S_22")
         # U_2 = (X_2 - Q_1 S_12) S_22^{-1}
         U = bk.right_solve(X2 - bk.matmul(Q1, S12), S22)
-    else:
+    elif first_intra == "tsqr":
         # S_12 = Q_1^T X_2 ; [U_2, S_22] = TSQR(X_2 - Q_1 S_12)
         stats.sync("S_12 = Q_1^T X_2")
         S12 = bk.matmul(Q1.T, X2)
         U, S22 = tsqr_slot(bk, X2 - bk.matmul(Q1, S12), stats, "TSQR(V_2)")
+    else:
+        # S_12 = Q_1^T X_2 ; U_2 = X_2 - Q_1 S_12 (no intra-orthogonalization)
+        stats.sync("S_12 = Q_1^T X_2")
+        S12 = bk.matmul(Q1.T, X2)
+        U = X2 - bk.matmul(Q1, S12)
+        S22 = bk.eye(s)
     S_col, S_diag = S12, S22
     # the loop below handles block columns k+1 = 2..q; for k = 1 the S
     # coefficients come from the set-up above, afterwards from eq. (1)
@@ -193,10 +205,14 @@ def _one_or_two_sync(X, s, bk, stats, first_intra):
                 S_diag = _chol(bk, T - bk.matmul(S_col.T, S_col), k,
                                "S_{k+1,k+1}")
                 U = bk.right_solve(Xk1 - bk.matmul(Qk, S_col), S_diag)
-            else:
+            elif first_intra == "tsqr":
                 # [U_{k+1}, S_{k+1,k+1}] = TSQR(X_{k+1} - Q_k S)
                 U, S_diag = tsqr_slot(bk, Xk1 - bk.matmul(Qk, S_col), stats,
                                       f"TSQR(V_{k+1})")
+            else:
+                # U_{k+1} = X_{k+1} - Q_k S, S_{k+1,k+1} = I
+                U = Xk1 - bk.matmul(Qk, S_col)
+                S_diag = bk.eye(s)
         if k < q - 1:
             # [Y Z_k; Omega P_{k+1}] = [Q_k U_{k+1}]^T [U_{k+1} X_{k+2}]
             # (and T_{k+2} = X_{k+2}^T X_{k+2} in the same sync, P-1S only)
@@ -234,8 +250,17 @@ def bcgs_p_2s(X, s, bk=FP64, stats=None):
     return _one_or_two_sync(X, s, bk, stats, "tsqr")
 
 
+def bcgs_i_plus_1s(X, s, bk=FP64, stats=None):
+    """BCGSI+1s (section 2.2; Table 1): Alg. 2 without the Cholesky factor
+    of the first intra-orthogonalization; one sync per block column, LOO
+    O(u) kappa^2 under O(u) kappa^3 <= 1."""
+    stats = stats if stats is not None else Stats()
+    return _one_or_two_sync(X, s, bk, stats, "none")
+
+
 VARIANTS = {
     "bcgsi+": bcgs_i_plus,
+    "bcgsi+1s": bcgs_i_plus_1s,
     "p-2s": bcgs_p_2s,
     "p-1s": bcgs_p_1s,
     "pipi+": bcgs_pipi_plus,

@@ -41,7 +41,8 @@ def _exact_checks(X, Q, R):
     return res, loo, lower, dmin
 
 
-@pytest.mark.parametrize("variant", ["bcgsi+", "p-2s", "p-1s", "pipi+"])
+@pytest.mark.parametrize("variant", ["bcgsi+", "p-2s", "p-1s", "pipi+",
+                                     "bcgsi+1s"])
 @pytest.mark.parametrize("m,n,s", SHAPES)
 def test_variant_is_the_qr_factorization(variant, m, n, s):
     X = _rand(m, n, seed=m * 100 + n * 10 + s)
@@ -85,7 +86,8 @@ def _table1(golden):
     return rows
 
 
-@pytest.mark.parametrize("variant", ["bcgsi+", "p-2s", "p-1s", "pipi+"])
+@pytest.mark.parametrize("variant", ["bcgsi+", "p-2s", "p-1s", "pipi+",
+                                     "bcgsi+1s"])
 def test_sync_counts_match_table1(variant, golden):
     """Each extra block column costs exactly Table 1's number of syncs."""
     coef = _table1(golden)[variant][0]
