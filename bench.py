@@ -7,8 +7,11 @@ reductions) of the synthetic workload, with X already resident in HBM.
 
 Default workload: m = 4,194,304 rows, n = 256 columns, block size s = 16,
 X = U diag(logspace(0, -8, 256)) V^T (kappa = 1e8), FP64.  The headline
-variant is BCGSI+P-1S; BCGSI+ and BCGSI+P-2S are timed on the same X for
-the speedups.  Prints one JSON line.
+variant is BCGSI+P-1S; BCGSI+, BCGSI+P-2S, BCGS-PIPI+ and BCGSI+1s are
+timed on the same X for the speedups.  Then the batched workload (256
+uneven problems in one graph launch) and the served stream (Poisson
+arrivals through the request queue, p50/p99), and the oracle on a sample
+of X as the CPU baseline.  Prints one JSON line.
 
     python bench.py [--steps K] [--warmup W] [--workload tall|tall-k6|sweep]
 """
@@ -388,7 +391,7 @@ def main():
     ap.add_argument("--workload", default="tall")
     ap.add_argument("--m", type=int, default=None)
     ap.add_argument("--s", type=int, default=None)
-    ap.add_argument("--variants", default="p-1s,bcgsi+,p-2s")
+    ap.add_argument("--variants", default="p-1s,bcgsi+,p-2s,pipi+,bcgsi+1s")
     ap.add_argument("--cpu-rows", type=int, default=1 << 20)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-check", action="store_true")
@@ -482,6 +485,12 @@ def main():
     if "p-2s" in results and "bcgsi+" in results:
         out["speedup_p2s_vs_bcgsi+"] = round(
             results["bcgsi+"]["ms"] / results["p-2s"]["ms"], 3)
+    if "bcgsi+" in results:
+        # every variant against BCGSI+ on the same X (Table 2's comparison
+        # on one GPU), with its status and LOO in "variants"
+        out["speedups_vs_bcgsi+"] = {
+            v: round(results["bcgsi+"]["ms"] / r["ms"], 3)
+            for v, r in results.items()}
     out["variants"] = {k: {kk: vv for kk, vv in r.items() if kk != "_agg"}
                        for k, r in results.items()}
     out["p99_latency_ms"] = None

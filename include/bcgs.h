@@ -49,7 +49,15 @@ typedef enum {
     /* BCGSI+P-1S: Alg. 2, one synchronization per block column, Pythagorean
      * Cholesky for both intra-orthogonalizations and delayed normalization
      * through eq. (1) (section 2.2). */
-    BCGS_P_1S = 2
+    BCGS_P_1S = 2,
+    /* BCGS-PIPI+: Alg. 1, Pythagorean Cholesky for both
+     * intra-orthogonalizations, 2 synchronizations per block column
+     * (section 2.1; 2q - 1 in all with TSQR(X_1)). */
+    BCGS_PIPI_PLUS = 3,
+    /* BCGSI+1s: Alg. 2 without the first intra-orthogonalization
+     * (S_{k,k} = I: U_k = X_k - Q S is not scaled), one synchronization per
+     * block column; LOO O(u) kappa^2 (section 2.2; Table 1). */
+    BCGS_I_PLUS_1S = 4
 } bcgs_variant;
 
 /* Arithmetic of the streamed m-row data.  BCGS_FP64: everything in binary64.
@@ -123,8 +131,9 @@ size_t bcgs_workspace_size(int64_t m, int64_t n, int64_t s,
 
 /* Number of device-wide reductions ("synchronization points", section 1)
  * the factorization of an m x n matrix with block width s performs:
- * q + 1 for BCGSI+P-1S, 2q for BCGSI+P-2S, 4q - 3 for BCGSI+ (Table 1 gives
- * the per-block-column rates q, 2q, 4q).  -1 on invalid arguments. */
+ * q + 1 for BCGSI+P-1S and BCGSI+1s, 2q for BCGSI+P-2S, 2q - 1 for
+ * BCGS-PIPI+, 4q - 3 for BCGSI+ (Table 1 gives the per-block-column rates
+ * q, q, 2q, 2q, 4q).  -1 on invalid arguments. */
 int32_t bcgs_sync_count(int64_t m, int64_t n, int64_t s,
                         bcgs_variant variant);
 

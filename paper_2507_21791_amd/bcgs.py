@@ -14,7 +14,7 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "_lib", "libbcgs.so")
 
-VARIANTS = {"bcgsi+": 0, "p-2s": 1, "p-1s": 2}
+VARIANTS = {"bcgsi+": 0, "p-2s": 1, "p-1s": 2, "pipi+": 3, "bcgsi+1s": 4}
 PRECISIONS = {"fp64": 0, "fp32-bulk": 1}
 STATUS = {0: "ok", 1: "invalid argument", 2: "Cholesky breakdown",
           3: "out of device memory", 4: "HIP runtime error", 5: "queue full",

@@ -171,7 +171,7 @@ hipError_t launch_fill(double* p, int64_t rows, int64_t cols, int64_t ld,
 enum EpiMode : int {
   EPI_S_ONLY = 0,     // C2 <- gram(0:js, 0:s)                      (S)
   EPI_Y_ONLY = 1,     // C1 <- gram(0:js, 0:s)                      (Y)
-  EPI_P1S_INIT = 2,   // [S_12; T_2]: C2 <- S_12, T2 <- chol(T_2 - S^T S)
+  EPI_S_CHOL = 2,     // [S; T] of block j: C2 <- S, T2 <- chol(T - S^T S)
   EPI_ONE_SYNC = 3,   // after [Q U]^T [U E]: Y_kk, R block column, eq. (1)
   EPI_R_ASSEMBLE = 4, // BCGSI+: R block column from C2, C1, T2, T1
 };
@@ -196,6 +196,7 @@ struct EpiArgs {
   int f2_mode, f2_rows;   // F2 from (C2, T2)
   int fold12;             // the next pass runs both updates on the staged
                           // columns: fold F1 into F2's rows [0, f1_rows + s)
+  int unit_s;             // BCGSI+1s: S_{j+1,j+1} = I (T2 <- I)
   double* r; int64_t ldr;
   bcgs_info* info;
 };

@@ -37,7 +37,7 @@ size_t pass_lds_bytes(const PassArgs<T>& a);
 static bool valid_args(int64_t m, int64_t n, int64_t s, int variant,
                        int precision) {
   if (s < 1 || s > kMaxS || n < 1 || m < n || n % s != 0) return false;
-  if (variant < BCGS_I_PLUS || variant > BCGS_P_1S) return false;
+  if (variant < BCGS_I_PLUS || variant > BCGS_I_PLUS_1S) return false;
   if (precision != BCGS_FP64 && precision != BCGS_FP32_BULK) return false;
   if (m > (int64_t(1) << 40)) return false;
   return true;
@@ -84,7 +84,9 @@ static int planned_syncs(int variant, int q) {
   if (q == 1) return 1;
   switch (variant) {
     case BCGS_P_1S: return q + 1;
+    case BCGS_I_PLUS_1S: return q + 1;
     case BCGS_P_2S: return 2 * q;
+    case BCGS_PIPI_PLUS: return 2 * q - 1;
     default: return 4 * q - 3;
   }
 }
@@ -226,7 +228,8 @@ struct Run {
   // With both f1 and f2 the next pass runs both block updates on the
   // staged columns, so F1 is folded into F2 (fold_coefs).
   void epi(int mode, int j, bool has_e, bool chol_s, int f1 = COEF_NONE,
-           int f1_rows = 0, int f2 = COEF_NONE, int f2_rows = 0) {
+           int f1_rows = 0, int f2 = COEF_NONE, int f2_rows = 0,
+           bool unit_s = false) {
     EpiArgs e{};
     e.mode = mode; e.s = p.s; e.sp = p.sp; e.j = j;
     e.has_e = has_e; e.chol_s = chol_s;
@@ -237,6 +240,7 @@ struct Run {
     e.f1_mode = f1; e.f1_rows = f1_rows;
     e.f2_mode = f2; e.f2_rows = f2_rows;
     e.fold12 = f1 != COEF_NONE && f2 != COEF_NONE;
+    e.unit_s = unit_s;
     e.r = R; e.ldr = ldr; e.info = info;
     check(launch_epilogue(e, st));
   }
@@ -263,17 +267,21 @@ struct Run {
     tsqr(xb(0), ldx, qb(0), R, 1, ldr);
     if (q == 1) return;
     if (p.variant == BCGS_I_PLUS) { run_i_plus(); return; }
-    const bool one = p.variant == BCGS_P_1S;
+    if (p.variant == BCGS_PIPI_PLUS) { run_pipi_plus(); return; }
+    // BCGSI+1s runs the P-1S schedule with S_{j,j} = I: unscaled U, no T
+    const bool unit = p.variant == BCGS_I_PLUS_1S;
+    const bool one = p.variant == BCGS_P_1S || unit;
+    const bool chol1 = p.variant == BCGS_P_1S;
     {
       Pass d;
       d.nq = s; d.f = xb(1); d.ldf = ldx;
       d.gram = true;
       d.gb0 = s; d.gbn = s;                   // [Q_0 X_1]^T X_1
-      d.needed = one ? 2 * s * s : s * s;     // P-2S needs Q_0^T X_1 only
+      d.needed = chol1 ? 2 * s * s : s * s;   // P-2S needs Q_0^T X_1 only
       pass(d);
-      // next: U_1 = (X_1 - Q_0 S_01) S_11^{-1} (P-1S) or V_1 = X_1 - Q_0 S_01
-      epi(one ? EPI_P1S_INIT : EPI_S_ONLY, 1, false, false, COEF_NONE, 0,
-          one ? COEF_SCALED : COEF_UNSCALED, s);
+      // next: U_1 = (X_1 - Q_0 S_01) S_11^{-1} (P-1S) or X_1 - Q_0 S_01
+      epi(chol1 ? EPI_S_CHOL : EPI_S_ONLY, 1, false, false, COEF_NONE, 0,
+          chol1 ? COEF_SCALED : COEF_UNSCALED, s, unit);
     }
     for (int j = 1; j < q; ++j) {
       const bool has_e = j < q - 1;
@@ -283,14 +291,17 @@ struct Run {
         d.upd1 = j >= 2;
         d.f = xb(j); d.ldf = ldx;
         d.upd2 = true; d.dst2 = qb(j);
+        d.scaled2 = chol1;
         if (has_e) { d.e = xb(j + 1); d.lde = ldx; }
         d.gram = true; d.gb0 = j * s; d.gbn = has_e ? 2 * s : s;
         d.skip_eu = has_e;
-        d.needed = (int64_t)(j + 1) * s * d.gbn + (has_e ? s * s : 0);
+        d.needed = (int64_t)(j + 1) * s * d.gbn +
+                   (has_e && chol1 ? s * s : 0);
         pass(d);
         // next: Q_j from U_j (Y, Y_jj) and U_{j+1} from X_{j+1} (S, S_jj)
-        epi(EPI_ONE_SYNC, j, has_e, true, COEF_SCALED, j * s,
-            has_e ? COEF_SCALED : COEF_NONE, (j + 1) * s);
+        epi(EPI_ONE_SYNC, j, has_e, chol1, COEF_SCALED, j * s,
+            has_e ? (chol1 ? COEF_SCALED : COEF_UNSCALED) : COEF_NONE,
+            (j + 1) * s, unit);
       } else {
         Pass u;                       // Q_{j-1} and V_j = X_j - Q S
         u.nq = j * s; u.upd1 = j >= 2;
@@ -309,6 +320,34 @@ struct Run {
         epi(EPI_ONE_SYNC, j, has_e, false, COEF_SCALED, j * s,
             has_e ? COEF_UNSCALED : COEF_NONE, (j + 1) * s);
       }
+    }
+    Pass fin;                         // Q_{q-1} = (U - Q Y) Y_kk^{-1}
+    fin.nq = q * s; fin.upd1 = true;
+    pass(fin);
+  }
+
+  // BCGS-PIPI+ (Alg. 1): two reductions per block column.  Forming Q_{j-1}
+  // from U_{j-1} is fused into the first pass of block column j.
+  void run_pipi_plus() {
+    const int s = p.s, q = p.q;
+    for (int j = 1; j < q; ++j) {
+      Pass a1;                        // [S; T] = [Q_{0:j-1} X_j]^T X_j
+      a1.nq = j * s; a1.upd1 = j >= 2;
+      a1.f = xb(j); a1.ldf = ldx;
+      a1.gram = true; a1.gb0 = j * s; a1.gbn = s;
+      a1.needed = (int64_t)(j + 1) * s * s;
+      pass(a1);
+      // S_jj = chol(T - S^T S); F2 for U_j = (X_j - Q S) S_jj^{-1}
+      epi(EPI_S_CHOL, j, false, false, COEF_NONE, 0, COEF_SCALED, j * s);
+      Pass a2;                        // U_j; [Y; Omega] = [Q U_j]^T U_j
+      a2.nq = j * s;
+      a2.f = xb(j); a2.ldf = ldx;
+      a2.upd2 = true; a2.dst2 = qb(j);
+      a2.gram = true; a2.gb0 = j * s; a2.gbn = s;
+      a2.needed = (int64_t)(j + 1) * s * s;
+      pass(a2);
+      // Y_jj = chol(Omega - Y^T Y), R block column, F1 for Q_j
+      epi(EPI_ONE_SYNC, j, false, false, COEF_SCALED, j * s);
     }
     Pass fin;                         // Q_{q-1} = (U - Q Y) Y_kk^{-1}
     fin.nq = q * s; fin.upd1 = true;

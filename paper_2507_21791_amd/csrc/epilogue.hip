@@ -256,6 +256,13 @@ __device__ void gram_products(const EpiArgs& a, int js, bool has_e,
   __syncthreads();
 }
 
+__device__ void store_identity(double* dst, int sp, int s) {
+  for (int e = threadIdx.x; e < sp * sp; e += kThreads) {
+    const int i = e / sp, l = e % sp;
+    dst[e] = (i == l && i < s) ? 1.0 : 0.0;
+  }
+}
+
 __device__ void store_tri(double* dst, int sp, int s, const double* src) {
   for (int e = threadIdx.x; e < sp * sp; e += kThreads) {
     const int i = e / sp, l = e % sp;
@@ -466,6 +473,7 @@ __device__ void epilogue_body(EpiArgs a, EpiSmem& sm) {
       const int i = e / sp, c = e % sp;
       dst[e] = c < s ? gram_at(a, i, c) : 0.0;
     }
+    if (a.unit_s) store_identity(a.t2, sp, s);
     return;
   }
 
@@ -476,20 +484,28 @@ __device__ void epilogue_body(EpiArgs a, EpiSmem& sm) {
     return;
   }
 
-  if (a.mode == EPI_P1S_INIT) {
-    // gram rows [0,s) = S_12, rows [s,2s) = T_2 (columns [0,s))
-    for (int e = tid; e < s * sp; e += kThreads) {
+  if (a.mode == EPI_S_CHOL) {
+    // gram rows [0, js) = S_{1:j,j+1}, rows [js, js+s) = T_{j+1}
+    // (columns [0, s)); S_{j+1,j+1} = chol(T - S^T S)
+    for (int e = tid; e < js * sp; e += kThreads) {
       const int i = e / sp, c = e % sp;
       a.c2[e] = c < s ? gram_at(a, i, c) : 0.0;
     }
-    for (int e = tid; e < s * s; e += kThreads) {
-      const int x = e / s, y = e % s;
-      double acc = gram_at(a, s + x, y);
-      for (int k = 0; k < s; ++k) acc -= gram_at(a, k, x) * gram_at(a, k, y);
-      sm.A[e] = acc;
+    if constexpr (S == 4 || S == 8 || S == 16) {
+      double ss = 0.0, unused1 = 0.0, unused2 = 0.0;
+      gram_products<S>(a, js, false, sm.B, ss, unused1, unused2);
+      if (tid < S * S) sm.A[tid] = gram_at(a, js + tid / S, tid % S) - ss;
+    } else {
+      for (int e = tid; e < s * s; e += kThreads) {
+        const int x = e / s, y = e % s;
+        double acc = gram_at(a, js + x, y);
+        for (int k = 0; k < js; ++k)
+          acc -= gram_at(a, k, x) * gram_at(a, k, y);
+        sm.A[e] = acc;
+      }
     }
     __syncthreads();
-    chol<S>(sm, s, a.info, 1, 0);
+    chol<S>(sm, s, a.info, a.j, 0);
     store_tri(a.t2, sp, s, sm.A);
     return;
   }
@@ -592,6 +608,10 @@ __device__ void epilogue_body(EpiArgs a, EpiSmem& sm) {
     double v = 0.0;
     if (c < s) v = i < js ? gram_at(a, i, s + c) : sm.B[(i - js) * s + c];
     a.c2[e] = v;
+  }
+  if (a.unit_s) {                     // BCGSI+1s: S_{j+1,j+1} = I
+    store_identity(a.t2, sp, s);
+    return;
   }
   if (!a.chol_s) return;
   // 4. S_{j+1,j+1} = chol(T - S^T S) with S = [Z; L]

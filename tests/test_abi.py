@@ -42,7 +42,8 @@ def test_info_struct_layout():
 
 @pytest.mark.parametrize("variant,q,want", [
     ("p-1s", 16, 17), ("p-2s", 16, 32), ("bcgsi+", 16, 61),
-    ("p-1s", 1, 1), ("p-2s", 1, 1), ("bcgsi+", 1, 1), ("p-1s", 2, 3)])
+    ("p-1s", 1, 1), ("p-2s", 1, 1), ("bcgsi+", 1, 1), ("p-1s", 2, 3),
+    ("pipi+", 16, 31), ("bcgsi+1s", 16, 17), ("pipi+", 1, 1)])
 def test_sync_counts(variant, q, want):
     assert bcgs.sync_count(1000, 4 * q, 4, variant) == want
 

@@ -14,6 +14,8 @@ from parity import compare, host, log, run_gpu, to_device
 
 pytestmark = pytest.mark.gpu
 VARIANTS = ["bcgsi+", "p-2s", "p-1s"]
+# with BCGS-PIPI+ (Alg. 1) and BCGSI+1s (section 2.2), the rest of Table 1
+VARIANTS5 = VARIANTS + ["pipi+", "bcgsi+1s"]
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -26,7 +28,7 @@ def _lib():
     bcgs.lib().bcgs_release()
 
 
-@pytest.mark.parametrize("variant", VARIANTS)
+@pytest.mark.parametrize("variant", VARIANTS5)
 def test_small_workload(variant):
     """2000 x 80, s = 8, kappa = 1e6 (10 block columns)."""
     w = W.WORKLOADS["small"]
@@ -47,7 +49,7 @@ SHAPES = [  # (m, n, s, decades)
 ]
 
 
-@pytest.mark.parametrize("variant", VARIANTS)
+@pytest.mark.parametrize("variant", VARIANTS5)
 @pytest.mark.parametrize("m,n,s,dec", SHAPES)
 def test_shapes(m, n, s, dec, variant):
     log(f"[gpu] shape m={m} n={n} s={s} kappa=1e{dec} {variant}")
@@ -57,7 +59,7 @@ def test_shapes(m, n, s, dec, variant):
 
 
 @pytest.mark.parametrize("decades", [6, 8])
-@pytest.mark.parametrize("variant", VARIANTS)
+@pytest.mark.parametrize("variant", VARIANTS + ["pipi+"])
 def test_tall_reduced_rows(variant, decades):
     """The 4M x 256, s = 16 workload's column structure at 2^16 + 37 rows."""
     m = (1 << 16) + 37
@@ -80,7 +82,7 @@ def test_sweep_reduced_rows(variant, s):
     compare(X, s, variant, host(Qg), host(Rg), info)
 
 
-@pytest.mark.parametrize("variant", VARIANTS)
+@pytest.mark.parametrize("variant", VARIANTS5)
 def test_exact_case_bitwise(variant):
     """Scaled permuted identity: every step is exact, so the GPU must return
     R = diag(2^e) and Q = X diag(2^-e) bit for bit (same closed form the
@@ -131,7 +133,7 @@ def test_breakdown_rank_deficient(variant):
         assert abs(info.value) <= 64 * 8 * 2.0 ** -53 * np.linalg.norm(X, 2) ** 2
 
 
-@pytest.mark.parametrize("variant", VARIANTS)
+@pytest.mark.parametrize("variant", VARIANTS5)
 def test_bitwise_repeatable_and_sync_count(variant):
     from paper_2507_21791_amd import bcgs
     log(f"[gpu] repeatability {variant}")
