@@ -66,13 +66,13 @@ def accuracy(X, Q, R, chunk=1 << 16):
     return loo, num / den
 
 
-def time_variant(X, s, variant, steps, warmup, Q, R):
+def time_variant(X, s, variant, steps, warmup, Q, R, precision="fp64"):
     import torch
     from paper_2507_21791_amd import bcgs
     m, n = X.shape
-    ws = bcgs.Workspace(m, n, s, variant, "fp64", X.device)
+    ws = bcgs.Workspace(m, n, s, variant, precision, X.device)
     for _ in range(warmup):
-        bcgs.qr(X, s, variant, Q=Q, R=R, ws=ws)
+        bcgs.qr(X, s, variant, precision, Q=Q, R=R, ws=ws)
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
     bcgs.profile_start(stream)
@@ -81,7 +81,7 @@ def time_variant(X, s, variant, steps, warmup, Q, R):
     torch.cuda.synchronize()
     e0.record(stream)
     for _ in range(steps):
-        bcgs.qr(X, s, variant, Q=Q, R=R, ws=ws)
+        bcgs.qr(X, s, variant, precision, Q=Q, R=R, ws=ws)
     e1.record(stream)
     torch.cuda.synchronize()
     recs = bcgs.profile_stop(stream)
@@ -112,6 +112,8 @@ def kernel_name(kind, tag):
         # tag 1WPBSTTPPN: waves, workgroups per CU, tile buffers, both
         # partial-sum areas, tile rows, Gram pairs per wave, B blocks
         nw, pc = (tag // 100000000) % 10, (tag // 10000000) % 10
+        f32 = pc >= 4                    # binary32 storage
+        pc -= 4 if f32 else 0
         nbuf, scr2 = (tag // 1000000) % 10, (tag // 100000) % 10
         reg = nbuf >= 5                  # tiles staged through registers
         nbuf -= 5 if reg else 0
@@ -120,12 +122,15 @@ def kernel_name(kind, tag):
                (16, 4): 272, (16, 8): 544}.get((tr, nw), 0)
         if (tr, nw, nbuf) == (16, 4, 4):
             cap = 272
+        if f32:
+            cap = {(32, 8): 544}.get((tr, nw), 272)
         gram = "true" if ntb else "false"
         r = "true" if reg else "false"
+        t = "float" if f32 else "double"
         if pc == 2:
-            return (f"pass16_kernel<{tr}, {nbuf}, {cap}, {maxp}, {gram}, "
-                    f"{max(ntb, 1)}, {r}>")
-        return (f"pass16_deep_kernel<{tr}, {nbuf}, {cap}, {nw}, "
+            return (f"pass16_kernel<{t}, {tr}, {nbuf}, {cap}, {maxp}, "
+                    f"{gram}, {max(ntb, 1)}, {r}>")
+        return (f"pass16_deep_kernel<{t}, {tr}, {nbuf}, {cap}, {nw}, "
                 f"{'true' if scr2 else 'false'}, {maxp}, {gram}, "
                 f"{max(ntb, 1)}, {r}>")
     if kind == "pass":
@@ -234,6 +239,36 @@ def cpu_baseline(Xd, s, rows, model_bytes_full, m_full):
                        f"model scaled to the sample"),
             "seconds": round(dt, 3),
             "breakdown": None if r.breakdown is None else r.breakdown.block}
+
+
+def bench_fp32_bulk(m, n, s, steps, warmup, fp64_ms):
+    """P-1S in the FP32-bulk form on the tall shape with kappa = 1e3 (inside
+    Table 1's u kappa^2 <= 1 with u = 2^-24), X rounded to binary32; LOO and
+    residual of the result in FP64, and the time against the FP64 form."""
+    import torch
+    from paper_2507_21791_amd import bcgs, workloads as W
+    X64 = W.conditioned_device(m, n, 3, seed=2)
+    X = torch.empty((n, m), dtype=torch.float32, device="cuda").t()
+    X.copy_(X64)
+    del X64
+    Q = bcgs.empty_fortran(m, n, torch.float32, "cuda")
+    R = bcgs.empty_fortran(n, n, torch.float64, "cuda")
+    ms, recs, info = time_variant(X, s, "p-1s", steps, warmup, Q, R,
+                                  "fp32-bulk")
+    agg = aggregate(recs, steps)
+    model_bytes = sum(a["bytes"] for a in agg)
+    loo, resid = accuracy(X.double(), Q.double(), R)
+    out = {"workload": f"m={m} n={n} s={s} kappa=1e3, P-1S, FP32-bulk",
+           "ms": round(ms, 4), "model_gb": round(model_bytes / 1e9, 3),
+           "gbs": round(model_bytes / (ms * 1e-3) / 1e9, 1),
+           "speedup_vs_fp64": round(fp64_ms / ms, 3),
+           "status": info.status, "loo": loo, "residual": resid,
+           "kernels": by_name(agg)[:6]}
+    log(f"[bench] fp32-bulk: {ms:.3f} ms {out['gbs']} GB/s status="
+        f"{info.status} loo={loo:.3g} residual={resid:.3g}")
+    del X, Q, R
+    torch.cuda.empty_cache()
+    return out
 
 
 def bench_batched(count, reps):
@@ -395,6 +430,7 @@ def main():
     ap.add_argument("--cpu-rows", type=int, default=1 << 20)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-check", action="store_true")
+    ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--batched-count", type=int, default=256)
     ap.add_argument("--no-served", action="store_true")
@@ -498,6 +534,9 @@ def main():
     Xhead = None if args.no_cpu else X[:rows].cpu()
     del X, Q, R
     torch.cuda.empty_cache()
+    if not args.no_fp32:
+        out["fp32_bulk"] = bench_fp32_bulk(m, n, s, args.steps, args.warmup,
+                                           head["ms"])
     if not args.no_batched:
         out["batched"] = bench_batched(args.batched_count, 3)
     if not args.no_served:

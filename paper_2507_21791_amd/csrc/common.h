@@ -151,6 +151,10 @@ hipError_t launch_pass16(const PassArgs<double>& a, int64_t m,
                          const Tuning& tune, hipStream_t st, int* tag,
                          int* G_out);
 int pass16_shape_count();
+// The same pass on binary32 storage (FP32-bulk form).
+hipError_t launch_pass16_f32(const PassArgs<float>& a, int64_t m,
+                             const Tuning& tune, hipStream_t st, int* tag,
+                             int* G_out);
 size_t pass16_lds_bytes(int ncols_p, int tr, int nw);
 
 struct EpiArgs;

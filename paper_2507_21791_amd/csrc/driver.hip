@@ -205,12 +205,13 @@ struct Run {
     int tag = 0;
     prof_begin(BCGS_KERNEL_PASS, -1, esz * mr * cols_rw, flops);
     hipError_t e = hipErrorNotSupported;
-    if constexpr (sizeof(T) == 8) {
-      if (p.sp == 16) {
-        int g16 = 0;
+    if (p.sp == 16) {
+      int g16 = 0;
+      if constexpr (sizeof(T) == 8)
         e = launch_pass16(a, p.m, p.tune, st, &tag, &g16);
-        if (e != hipErrorNotSupported) G = g16;
-      }
+      else
+        e = launch_pass16_f32(a, p.m, p.tune, st, &tag, &g16);
+      if (e != hipErrorNotSupported) G = g16;
     }
     if (e == hipErrorNotSupported) e = launch_pass(a, G, st, &tag);
     check(e);

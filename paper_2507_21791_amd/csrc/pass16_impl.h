@@ -15,18 +15,46 @@ namespace bcgs {
 
 namespace p16 {
 
-constexpr int kMaxKF = 20;            // C fragments per update per wave
 
-// C fragments per update per wave of a shape with column capacity CAP
-__host__ __device__ constexpr int kf_of(int cap) { return cap > 272 ? 20 : 16; }
+// C fragments per update per wave of a shape with column capacity CAP:
+// binary64 shapes split K over 4 or 8 waves, binary32 shapes (twice the
+// rows per tile for the same bytes) over 2 or 4
+template <typename T>
+__host__ __device__ constexpr int kf_of(int cap) {
+  return sizeof(T) == 8 ? (cap > 272 ? 20 : 16) : (cap > 128 ? 36 : 16);
+}
 
 typedef double v4d __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
 
 // v_mfma_f64_16x16x4f64: A[l % 16][l / 16], B[l / 16][l % 16],
 // D[l / 16 + 4 v][l % 16]
 __device__ __forceinline__ v4d mfma16(double a, double b, v4d c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
+// v_mfma_f32_16x16x4f32: same operand layout, D[4 (l / 16) + v][l % 16]
+__device__ __forceinline__ v4f mfma16(float a, float b, v4f c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+// storage-type traits: the 16-byte vector, the MFMA accumulator, the row
+// of result value v at lane group lk
+template <typename T> struct Elt;
+template <> struct Elt<double> {
+  typedef double2 V16;
+  typedef v4d Acc;
+  static __device__ __forceinline__ int drow(int lk, int v) {
+    return lk + 4 * v;
+  }
+};
+template <> struct Elt<float> {
+  typedef float4 V16;
+  typedef v4f Acc;
+  static __device__ __forceinline__ int drow(int lk, int v) {
+    return 4 * lk + v;
+  }
+};
+template <typename T> constexpr int kEpg = 16 / (int)sizeof(T);
 
 // v_mfma_f64_4x4x4f64: four independent 4x4x4 products per wave.  With
 // lane l = i + 4 b + 16 k (operand A), l = j + 4 b + 16 k (operand B) and
@@ -36,17 +64,23 @@ __device__ __forceinline__ double mfma4(double a, double b, double c) {
   return __builtin_amdgcn_mfma_f64_4x4x4f64(a, b, c, 0, 0, 0);
 }
 
-// swizzle key of column c: a permutation of the granule index
-template <int TR>
+// swizzle key of column c: a permutation of the granule index (granule =
+// 16 bytes: 2 doubles or 4 floats; TR / kEpg granules per column)
+template <typename T, int TR>
 __device__ __forceinline__ int swz(int c) {
-  if (TR >= 32) return ((c & 1) << 3) | ((c >> 1) & 7);
-  return (c >> 1) & 7;
+  if constexpr (sizeof(T) == 8) {
+    if (TR >= 32) return ((c & 1) << 3) | ((c >> 1) & 7);
+    return (c >> 1) & 7;
+  } else {
+    return c & (TR / 4 - 1);
+  }
 }
 
-// LDS offset (in doubles) of element (row r, column c) of a tile
-template <int TR>
+// LDS offset (in elements) of element (row r, column c) of a tile
+template <typename T, int TR>
 __device__ __forceinline__ int at(int c, int r) {
-  return c * TR + (((r >> 1) ^ swz<TR>(c)) << 1) + (r & 1);
+  constexpr int E = kEpg<T>;
+  return c * TR + (((r / E) ^ swz<T, TR>(c)) * E) + (r % E);
 }
 
 // s_waitcnt vmcnt(n) (n <= 63), leaving the other counters alone
@@ -74,21 +108,26 @@ __device__ __forceinline__ void lds_barrier() {
   asm volatile("" ::: "memory");
 }
 
-struct Args {
+// T: storage type of the streamed columns; coefficients and Gram partials
+// are FP64 either way
+template <typename T>
+struct ArgsT {
   int64_t m;
   int s, ncols, ncols_p;
   int64_t rows_per_wg;
-  const double* q; int64_t ldq; int nq;
-  const double* f; int64_t ldf; int fcols;
-  const double* e; int64_t lde; int ecols;
-  int upd1, u1_c0; const double* c1; double* dst1; int64_t ldd1;
-  int upd2, u2_c0; const double* c2; double* dst2; int64_t ldd2;
+  const T* q; int64_t ldq; int nq;
+  const T* f; int64_t ldf; int fcols;
+  const T* e; int64_t lde; int ecols;
+  int upd1, u1_c0; const double* c1; T* dst1; int64_t ldd1;
+  int upd2, u2_c0; const double* c2; T* dst2; int64_t ldd2;
   int gram, ga_p, gb0, gbn_p, skip_a0, skip_b1;
   double* partial;
 };
+typedef ArgsT<double> Args;
 
-__device__ __forceinline__ const double* col_ptr(const Args& a, int c,
-                                                 int64_t* ld) {
+template <typename T>
+__device__ __forceinline__ const T* col_ptr(const ArgsT<T>& a, int c,
+                                            int64_t* ld) {
   if (c < a.nq) { *ld = a.ldq; return a.q + (int64_t)c * a.ldq; }
   c -= a.nq;
   if (c < a.fcols) { *ld = a.ldf; return a.f + (int64_t)c * a.ldf; }
@@ -98,37 +137,36 @@ __device__ __forceinline__ const double* col_ptr(const Args& a, int c,
 }
 
 // Synchronous staging of a short last tile: zero past the row count.
-template <int TR, int NW>
-__device__ void tile_sync(const Args& a, double* buf, int64_t r0, int rows) {
+template <typename T, int TR, int NW>
+__device__ void tile_sync(const ArgsT<T>& a, T* buf, int64_t r0, int rows) {
   for (int idx = threadIdx.x; idx < a.ncols * TR; idx += NW * 64) {
     const int c = idx / TR, r = idx % TR;
-    double v = 0.0;
+    T v = 0;
     if (r < rows) {
       int64_t ld;
-      const double* src = col_ptr(a, c, &ld);
+      const T* src = col_ptr(a, c, &ld);
       v = src[r0 + r];
     }
-    buf[at<TR>(c, r)] = v;
+    buf[at<T, TR>(c, r)] = v;
   }
 }
 
 // Sum the K-range partial products of one block update (scr: [KG][TR][17])
 // into the tile columns [uc0, uc0 + s) and into dst (rows < rows).
-template <int TR, int KG, int NW>
-__device__ __forceinline__ void combine(const Args& a, double* tile,
-                                        const double* scr, int uc0,
-                                        double* dst, int64_t ldd, int64_t r0,
-                                        int rows) {
+template <typename T, int TR, int KG, int NW>
+__device__ __forceinline__ void combine(const ArgsT<T>& a, T* tile,
+                                        const T* scr, int uc0, T* dst,
+                                        int64_t ldd, int64_t r0, int rows) {
   for (int t = threadIdx.x; t < TR * 16; t += NW * 64) {
     const int r = t % TR, c = t / TR;
     if (c >= a.s) continue;
-    double part[KG];
+    T part[KG];
 #pragma unroll
     for (int k = 0; k < KG; ++k) part[k] = scr[(k * TR + r) * 17 + c];
-    double sum = 0.0;
+    T sum = 0;
 #pragma unroll
     for (int k = 0; k < KG; ++k) sum += part[k];
-    tile[at<TR>(uc0 + c, r)] = sum;
+    tile[at<T, TR>(uc0 + c, r)] = sum;
     if (r < rows) dst[(int64_t)c * ldd + r0 + r] = sum;
   }
 }
@@ -153,32 +191,38 @@ __device__ __forceinline__ void combine(const Args& a, double* tile,
 // use, so the tile layout is identical.  Two buffers: tile t is computed
 // while tile t+1 is in registers; then tile t+1 goes to the other buffer
 // and the loads of tile t+2 are issued.
-template <int TR, int NBUF, int CAP, int PC, int NW, bool SCR2, int MAXP,
-          bool GRAM, int NTB, bool REG>
+template <typename T, int TR, int NBUF, int CAP, int PC, int NW, bool SCR2,
+          int MAXP, bool GRAM, int NTB, bool REG>
 struct Kernel {
-  static constexpr int KF = kf_of(CAP);
+  typedef ArgsT<T> Args;
+  typedef typename Elt<T>::V16 V16;
+  typedef typename Elt<T>::Acc Acc;
+  static constexpr int E = kEpg<T>;           // elements per 16 bytes
+  static constexpr int KF = kf_of<T>(CAP);
   static constexpr int MB = TR / 16;          // row blocks per tile
   static constexpr int KG = NW / MB;          // K ranges per update
   static constexpr int kTail = (4 + KG - 1) / KG;
-  static constexpr int CPI = 1024 / (TR * 8); // columns per copy instruction
+  static constexpr int CPI = 1024 / (TR * (int)sizeof(T));  // columns per
+                                                            // copy instr.
   static constexpr int IPW = ((CAP + CPI - 1) / CPI + NW - 1) / NW;
-  static constexpr int TE = CAP * TR;         // doubles per buffer
+  static constexpr int TE = CAP * TR;         // elements per buffer
   static_assert(CAP % CPI == 0, "buffer holds whole copy instructions");
+  static_assert(KG >= 1, "at least one wave per row block");
 
   // register-resident state of one wave
   struct State {
-    double c1f[KF], c2f[KF];           // shared K-steps (both updates)
-    double c2o[kTail];                 // update 2, steps over its own block
+    T c1f[KF], c2f[KF];                // shared K-steps (both updates)
+    T c2o[kTail];                      // update 2, steps over its own block
     int kb, ke, nks2, sq;
     int mb, kg;
-    double acc[MAXP][4];
+    T acc[MAXP][4];
     int npairs;
   };
 
   // direct-to-LDS copy of the full tile at rows r0 .. r0+TR-1
-  static __device__ __forceinline__ void dma(const Args& a, double* buf,
+  static __device__ __forceinline__ void dma(const Args& a, T* buf,
                                              int64_t r0) {
-    constexpr int kGran = TR / 2;                    // granules per column
+    constexpr int kGran = TR / E;                    // granules per column
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int ninst = (a.ncols + CPI - 1) / CPI;
@@ -188,8 +232,8 @@ struct Kernel {
       const int c = ins * CPI + lane / kGran;
       const int g = lane % kGran;
       int64_t ld;
-      const double* src = col_ptr(a, min(c, a.ncols - 1), &ld);
-      const int rr = (g ^ swz<TR>(c)) << 1;
+      const T* src = col_ptr(a, min(c, a.ncols - 1), &ld);
+      const int rr = (g ^ swz<T, TR>(c)) * E;
       __builtin_amdgcn_global_load_lds(src + r0 + rr, buf + ins * CPI * TR,
                                        16, 0, 0);
     }
@@ -197,8 +241,8 @@ struct Kernel {
 
   // register staging: the loads of the tile at rows r0 .. r0+TR-1
   static __device__ __forceinline__ void issue(const Args& a, int64_t r0,
-                                               double2 (&pend)[IPW]) {
-    constexpr int kGran = TR / 2;
+                                               V16 (&pend)[IPW]) {
+    constexpr int kGran = TR / E;
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int ninst = (a.ncols + CPI - 1) / CPI;
@@ -208,23 +252,30 @@ struct Kernel {
       const int c = ins * CPI + lane / kGran;
       const int g = lane % kGran;
       int64_t ld;
-      const double* src = col_ptr(a, min(c, a.ncols - 1), &ld);
-      const double* p = src + r0 + ((g ^ swz<TR>(c)) << 1);
-      pend[i].x = p[0];
-      pend[i].y = p[1];
+      const T* src = col_ptr(a, min(c, a.ncols - 1), &ld);
+      const T* p = src + r0 + (g ^ swz<T, TR>(c)) * E;
+      if constexpr (E == 2) {
+        pend[i].x = p[0];
+        pend[i].y = p[1];
+      } else {
+        pend[i].x = p[0];
+        pend[i].y = p[1];
+        pend[i].z = p[2];
+        pend[i].w = p[3];
+      }
     }
   }
 
   // ... and their LDS writes, where the direct copy would have put them
-  static __device__ __forceinline__ void commit(const Args& a, double* buf,
-                                                const double2 (&pend)[IPW]) {
+  static __device__ __forceinline__ void commit(const Args& a, T* buf,
+                                                const V16 (&pend)[IPW]) {
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int ninst = (a.ncols + CPI - 1) / CPI;
 #pragma unroll
     for (int i = 0; i < IPW; ++i) {
       const int ins = min(wave + NW * i, ninst - 1);
-      *reinterpret_cast<double2*>(buf + ins * CPI * TR + 2 * lane) = pend[i];
+      *reinterpret_cast<V16*>(buf + ins * CPI * TR + E * lane) = pend[i];
     }
   }
 
@@ -234,25 +285,25 @@ struct Kernel {
   // quarter of what the 4x4x4 form would need
   template <bool U1, bool U2>
   static __device__ __forceinline__ void updates(const Args& a, State& S,
-                                                 double* tile, double* scr,
+                                                 T* tile, T* scr,
                                                  int64_t r0, int rows) {
     const int lane = threadIdx.x & 63;
     const int li = lane & 15, lk = lane >> 4;
     // K-steps in uniform chunks of 4; inside a chunk the four fragment
     // loads are issued first; K-steps past ke read a valid address and
     // meet zero coefficient fragments, so no lane-divergent branches
-    v4d acc1 = {0.0, 0.0, 0.0, 0.0}, acc2 = {0.0, 0.0, 0.0, 0.0};
-    v4d acc1b = {0.0, 0.0, 0.0, 0.0}, acc2b = {0.0, 0.0, 0.0, 0.0};
+    Acc acc1 = {0, 0, 0, 0}, acc2 = {0, 0, 0, 0};
+    Acc acc1b = {0, 0, 0, 0}, acc2b = {0, 0, 0, 0};
     const int kcl = max(S.kb, S.ke - 1);
     const int row = S.mb * 16 + li;
 #pragma unroll
     for (int q = 0; q < KF / 4; ++q) {
       if (4 * q >= S.ke - S.kb) break;
-      double av[4];
+      T av[4];
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         const int k = min(S.kb + 4 * q + u, kcl);
-        av[u] = tile[at<TR>(4 * k + lk, row)];
+        av[u] = tile[at<T, TR>(4 * k + lk, row)];
       }
 #pragma unroll
       for (int u = 0; u < 4; u += 2) {
@@ -267,52 +318,53 @@ struct Kernel {
       for (int u = 0; u < kTail; ++u) {
         const int t = S.kg + KG * u;
         if (t < S.sq)
-          acc2b = mfma16(tile[at<TR>(4 * (S.nks2 + t) + lk, row)], S.c2o[u],
-                         acc2b);
+          acc2b = mfma16(tile[at<T, TR>(4 * (S.nks2 + t) + lk, row)],
+                         S.c2o[u], acc2b);
       }
     }
     acc1 += acc1b;
     acc2 += acc2b;
     // partial sums: scr[kg][row][col], row stride 17; result v at lane l is
-    // row mb*16 + lk + 4 v, column li
-    double* scr1 = scr;
-    double* scr2 = SCR2 ? scr + KG * TR * 17 : scr;
-    const int wbase = (S.kg * TR + S.mb * 16 + lk) * 17 + li;
+    // row mb*16 + drow(lk, v), column li
+    T* scr1 = scr;
+    T* scr2 = SCR2 ? scr + KG * TR * 17 : scr;
+    const int wbase = (S.kg * TR + S.mb * 16) * 17 + li;
     if (U1) {
 #pragma unroll
-      for (int v = 0; v < 4; ++v) scr1[wbase + 4 * v * 17] = acc1[v];
+      for (int v = 0; v < 4; ++v)
+        scr1[wbase + Elt<T>::drow(lk, v) * 17] = acc1[v];
     }
     if (U2 && (SCR2 || !U1)) {
 #pragma unroll
-      for (int v = 0; v < 4; ++v) scr2[wbase + 4 * v * 17] = acc2[v];
+      for (int v = 0; v < 4; ++v)
+        scr2[wbase + Elt<T>::drow(lk, v) * 17] = acc2[v];
     }
     lds_barrier();
-    if (U1) combine<TR, KG, NW>(a, tile, scr1, a.u1_c0, a.dst1, a.ldd1, r0, rows);
+    if (U1)
+      combine<T, TR, KG, NW>(a, tile, scr1, a.u1_c0, a.dst1, a.ldd1, r0,
+                             rows);
     if (U2 && (SCR2 || !U1))
-      combine<TR, KG, NW>(a, tile, scr2, a.u2_c0, a.dst2, a.ldd2, r0, rows);
+      combine<T, TR, KG, NW>(a, tile, scr2, a.u2_c0, a.dst2, a.ldd2, r0,
+                             rows);
     lds_barrier();
     if (!SCR2 && U1 && U2) {
       // one partial-sum area: the second update's round
 #pragma unroll
-      for (int v = 0; v < 4; ++v) scr[wbase + 4 * v * 17] = acc2[v];
+      for (int v = 0; v < 4; ++v)
+        scr[wbase + Elt<T>::drow(lk, v) * 17] = acc2[v];
       lds_barrier();
-      combine<TR, KG, NW>(a, tile, scr, a.u2_c0, a.dst2, a.ldd2, r0, rows);
+      combine<T, TR, KG, NW>(a, tile, scr, a.u2_c0, a.dst2, a.ldd2, r0,
+                             rows);
       lds_barrier();
     }
   }
 
   static __device__ __forceinline__ void process(const Args& a, State& S,
-                                                 double* tile, double* scr,
+                                                 T* tile, T* scr,
                                                  int64_t r0, int rows) {
     const int lane = threadIdx.x & 63;
     const int li = lane & 15, lk = lane >> 4;
-    // ---- block updates, as out^T = F^T tile^T in 4x4x4 blocks: the A
-    //      operand is the F fragment (F[4k + lk][li], kept in registers),
-    //      the B operand of instruction q holds rows mb*16 + 4 j + q (j =
-    //      lane & 3) of tile column 4k + lk, so a lane's four B values are
-    //      four consecutive rows (two 16-byte loads per K-step).  Output
-    //      q at lane l: row mb*16 + 4 (l & 3) + q, column 4 ((l >> 2) & 3) +
-    //      (l >> 4). ----
+    // ---- block updates (16x16x4 MFMA, see updates()) ----
     if (a.upd1 && a.upd2) updates<true, true>(a, S, tile, scr, r0, rows);
     else if (a.upd2) updates<false, true>(a, S, tile, scr, r0, rows);
     else if (a.upd1) updates<true, false>(a, S, tile, scr, r0, rows);
@@ -322,7 +374,35 @@ struct Kernel {
     //      (lane group lk takes rows kk + 2 lk and kk + 2 lk + 1).  Pair i of
     //      this wave is p = wave + NW i; since NW is a multiple of NTB, all
     //      pairs of a wave share the B block wave % NTB. ----
-    if (GRAM) {
+    if constexpr (GRAM && sizeof(T) == 4) {
+      // binary32: 16x16x4 MFMA per pair; the rows of a 16-row chunk are
+      // assigned to (K-step q, lane group lk) as row kk + 4 lk + q, the
+      // same for both operands, so one 16-byte load per operand feeds four
+      // MFMAs.  Result v at lane l: A column 4 lk + v, B column li.
+      const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+      const int bcol = a.gb0 + (wave % NTB) * 16 + li;
+#pragma unroll
+      for (int kk = 0; kk < TR; kk += 16) {
+        const int r = kk + 4 * lk;
+        const V16 bq = *reinterpret_cast<const V16*>(tile + at<T, TR>(bcol, r));
+#pragma unroll
+        for (int i = 0; i < MAXP; ++i) {
+          const int p = wave + NW * i;
+          if (p < S.npairs) {          // wave-uniform
+            const V16 af = *reinterpret_cast<const V16*>(
+                tile + at<T, TR>((p / NTB) * 16 + li, r));
+            Acc acc = {S.acc[i][0], S.acc[i][1], S.acc[i][2], S.acc[i][3]};
+            acc = mfma16(af.x, bq.x, acc);
+            acc = mfma16(af.y, bq.y, acc);
+            acc = mfma16(af.z, bq.z, acc);
+            acc = mfma16(af.w, bq.w, acc);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) S.acc[i][v] = acc[v];
+          }
+        }
+        asm volatile("" ::: "memory");
+      }
+    } else if constexpr (GRAM) {
       const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
       const int bcol = a.gb0 + (wave % NTB) * 16 + 4 * (lane & 3);
 #pragma unroll
@@ -331,19 +411,20 @@ struct Kernel {
         double2 bq[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q)
-          bq[q] = *reinterpret_cast<const double2*>(tile + at<TR>(bcol + q, r));
+          bq[q] = *reinterpret_cast<const double2*>(
+              tile + at<T, TR>(bcol + q, r));
 #pragma unroll
         for (int i = 0; i < MAXP; ++i) {
           const int p = wave + NW * i;
           if (p < S.npairs) {          // wave-uniform
             const double2 af = *reinterpret_cast<const double2*>(
-                tile + at<TR>((p / NTB) * 16 + li, r));
+                tile + at<T, TR>((p / NTB) * 16 + li, r));
 #pragma unroll
             for (int q = 0; q < 4; ++q)
-              S.acc[i][q] = mfma4(af.x, bq[q].x, S.acc[i][q]);
+              S.acc[i][q] = mfma4(af.x, bq[q].x, (double)S.acc[i][q]);
 #pragma unroll
             for (int q = 0; q < 4; ++q)
-              S.acc[i][q] = mfma4(af.y, bq[q].y, S.acc[i][q]);
+              S.acc[i][q] = mfma4(af.y, bq[q].y, (double)S.acc[i][q]);
           }
         }
         asm volatile("" ::: "memory");
@@ -355,8 +436,8 @@ struct Kernel {
   // t + NBUF - 1 goes into the buffer tile t - 1 used, tile t is computed
   template <int I>
   static __device__ __forceinline__ void step(const Args& a, State& S,
-                                              double* const (&bufs)[4],
-                                              double* scr, int64_t row0,
+                                              T* const (&bufs)[4],
+                                              T* scr, int64_t row0,
                                               int64_t t) {
     __builtin_amdgcn_s_waitcnt(P16_VM((NBUF - 2) * IPW));
     lds_barrier();
@@ -369,10 +450,10 @@ struct Kernel {
   // in registers (when it exists)
   template <int I>
   static __device__ __forceinline__ void step_reg(const Args& a, State& S,
-                                                  double* const (&bufs)[4],
-                                                  double* scr, int64_t row0,
+                                                  T* const (&bufs)[4],
+                                                  T* scr, int64_t row0,
                                                   int64_t t, int64_t nfull,
-                                                  double2 (&pend)[IPW]) {
+                                                  V16 (&pend)[IPW]) {
     process(a, S, bufs[I], scr, row0 + t * TR, TR);
     if (t + 1 < nfull) commit(a, bufs[I ^ 1], pend);
     if (t + 2 < nfull) issue(a, row0 + (t + 2) * TR, pend);
@@ -380,12 +461,12 @@ struct Kernel {
   }
 
   static __device__ __forceinline__ void run(const Args& a) {
-    __shared__ double b0[TE];
-    __shared__ double b1[TE];
-    __shared__ double b2[NBUF > 2 ? TE : 1];
-    __shared__ double b3[NBUF > 3 ? TE : 1];
-    __shared__ double scr[(SCR2 ? 2 : 1) * KG * TR * 17];
-    double* const bufs[4] = {b0, b1, b2, b3};
+    __shared__ T b0[TE];
+    __shared__ T b1[TE];
+    __shared__ T b2[NBUF > 2 ? TE : 1];
+    __shared__ T b3[NBUF > 3 ? TE : 1];
+    __shared__ T scr[(SCR2 ? 2 : 1) * KG * TR * 17];
+    T* const bufs[4] = {b0, b1, b2, b3};
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform
     const int li = lane & 15, lk = lane >> 4;
@@ -412,14 +493,14 @@ struct Kernel {
     for (int i = 0; i < KF; ++i) {
       const int k = S.kb + i;
       const int row = 4 * k + lk;
-      S.c1f[i] = (k < S.ke && k < nks1) ? a.c1[row * 16 + li] : 0.0;
-      S.c2f[i] = (k < S.ke && k < S.nks2) ? a.c2[row * 16 + li] : 0.0;
+      S.c1f[i] = (k < S.ke && k < nks1) ? (T)a.c1[row * 16 + li] : T(0);
+      S.c2f[i] = (k < S.ke && k < S.nks2) ? (T)a.c2[row * 16 + li] : T(0);
     }
 #pragma unroll
     for (int u = 0; u < kTail; ++u) {
       const int t = S.kg + KG * u;
       S.c2o[u] = (a.upd2 && t < S.sq)
-                     ? a.c2[(4 * (S.nks2 + t) + lk) * 16 + li] : 0.0;
+                     ? (T)a.c2[(4 * (S.nks2 + t) + lk) * 16 + li] : T(0);
     }
     // ---- Gram pairs p = wave + NW i, p = (A block) * NTB + (B block) ----
     const int nta = a.ga_p >> 4;
@@ -427,17 +508,17 @@ struct Kernel {
 #pragma unroll
     for (int i = 0; i < MAXP; ++i)
 #pragma unroll
-      for (int q = 0; q < 4; ++q) S.acc[i][q] = 0.0;
+      for (int q = 0; q < 4; ++q) S.acc[i][q] = 0;
     // the fragment loads above complete here, so no wait for them is left
     // pending inside the tile loop, where it would drain the copies
     __builtin_amdgcn_s_waitcnt(0);
     // zero the columns past the copied ones (multiplied by zero weights
     // in the updates; their Gram entries are not read)
     for (int idx = a.ncols_p * TR + tid; idx < TE; idx += NW * 64) {
-      b0[idx] = 0.0;
-      b1[idx] = 0.0;
-      if (NBUF > 2) b2[idx] = 0.0;
-      if (NBUF > 3) b3[idx] = 0.0;
+      b0[idx] = 0;
+      b1[idx] = 0;
+      if (NBUF > 2) b2[idx] = 0;
+      if (NBUF > 3) b3[idx] = 0;
     }
 
     // ---- full tiles ----
@@ -445,7 +526,7 @@ struct Kernel {
     int64_t t = 0, issued = 0;
     if constexpr (REG) {
       static_assert(NBUF == 2, "register staging uses two buffers");
-      double2 pend[IPW];
+      V16 pend[IPW];
       if (nfull >= 1) {
         issue(a, row_begin, pend);
         commit(a, b0, pend);
@@ -476,7 +557,7 @@ struct Kernel {
     // the last few tiles one at a time, without overlap
     for (; t < nfull; ++t) {
       const int bi = (int)(t % NBUF);
-      double* tile = bi == 0 ? b0 : bi == 1 ? b1 : bi == 2 ? b2 : b3;
+      T* tile = bi == 0 ? b0 : bi == 1 ? b1 : bi == 2 ? b2 : b3;
       if (t >= issued) dma(a, tile, row_begin + t * TR);
       __builtin_amdgcn_s_waitcnt(0);
       lds_barrier();
@@ -487,7 +568,7 @@ struct Kernel {
     if (rt < row_end) {
       __builtin_amdgcn_s_waitcnt(0);
       lds_barrier();
-      tile_sync<TR, NW>(a, b0, rt, (int)(row_end - rt));
+      tile_sync<T, TR, NW>(a, b0, rt, (int)(row_end - rt));
       lds_barrier();
       process(a, S, b0, scr, rt, (int)(row_end - rt));
     }
@@ -500,47 +581,58 @@ struct Kernel {
         if (p >= S.npairs) continue;
         const int ta = (p / NTB) * 16, b = p % NTB;
         if (ta >= a.skip_a0 && b * 16 + 16 <= a.skip_b1) continue;
-        // acc[i][q] at lane l: A column ta + 4 ((l >> 2) & 3) + lk,
-        // B column b * 16 + 4 (l & 3) + q
+        if constexpr (sizeof(T) == 4) {
+          // acc[i][v] at lane l: A column ta + 4 lk + v, B column b*16 + li
 #pragma unroll
-        for (int q = 0; q < 4; ++q)
-          out[(size_t)(b * 16 + 4 * (lane & 3) + q) * a.ga_p + ta +
-              4 * ((lane >> 2) & 3) + lk] = S.acc[i][q];
+          for (int v = 0; v < 4; ++v)
+            out[(size_t)(b * 16 + li) * a.ga_p + ta + 4 * lk + v] =
+                (double)S.acc[i][v];
+        } else {
+          // acc[i][q] at lane l: A column ta + 4 ((l >> 2) & 3) + lk,
+          // B column b * 16 + 4 (l & 3) + q
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+            out[(size_t)(b * 16 + 4 * (lane & 3) + q) * a.ga_p + ta +
+                4 * ((lane >> 2) & 3) + lk] = S.acc[i][q];
+        }
       }
     }
   }
 };
 
 // two 4-wave workgroups per CU: at most 256 registers per lane
-template <int TR, int NBUF, int CAP, int MAXP, bool GRAM, int NTB, bool REG>
+template <typename T, int TR, int NBUF, int CAP, int MAXP, bool GRAM, int NTB,
+          bool REG>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
-void pass16_kernel(Args a) {
-  Kernel<TR, NBUF, CAP, 2, 4, false, MAXP, GRAM, NTB, REG>::run(a);
+void pass16_kernel(ArgsT<T> a) {
+  Kernel<T, TR, NBUF, CAP, 2, 4, false, MAXP, GRAM, NTB, REG>::run(a);
 }
 
 // one workgroup of NW waves per CU
-template <int TR, int NBUF, int CAP, int NW, bool SCR2, int MAXP, bool GRAM,
-          int NTB, bool REG>
+template <typename T, int TR, int NBUF, int CAP, int NW, bool SCR2, int MAXP,
+          bool GRAM, int NTB, bool REG>
 __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(NW / 4)))
-void pass16_deep_kernel(Args a) {
-  Kernel<TR, NBUF, CAP, 1, NW, SCR2, MAXP, GRAM, NTB, REG>::run(a);
+void pass16_deep_kernel(ArgsT<T> a) {
+  Kernel<T, TR, NBUF, CAP, 1, NW, SCR2, MAXP, GRAM, NTB, REG>::run(a);
 }
 
-template <int TR, int NBUF, int CAP, int PC, int NW, bool SCR2, int MAXP,
-          bool GRAM, int NTB, bool REG>
-static hipError_t go(const Args& a, int G, hipStream_t st, int* tag) {
-  // 1 W P B S TT PP N: waves, workgroups per CU, tile buffers (+5 with
-  // register staging), both partial-sum areas, tile rows, Gram pairs per
-  // wave, B blocks (0: no Gram)
-  *tag = 1000000000 + NW * 100000000 + PC * 10000000 +
-         (NBUF + (REG ? 5 : 0)) * 1000000 + (SCR2 ? 100000 : 0) + TR * 1000 +
-         MAXP * 10 + (GRAM ? NTB : 0);
+template <typename T, int TR, int NBUF, int CAP, int PC, int NW, bool SCR2,
+          int MAXP, bool GRAM, int NTB, bool REG>
+static hipError_t go(const ArgsT<T>& a, int G, hipStream_t st, int* tag) {
+  // 1 W P B S TT PP N: waves, workgroups per CU (+4 for binary32), tile
+  // buffers (+5 with register staging), both partial-sum areas, tile rows
+  // (mod 100), Gram pairs per wave, B blocks (0: no Gram)
+  *tag = 1000000000 + NW * 100000000 +
+         (PC + (sizeof(T) == 4 ? 4 : 0)) * 10000000 +
+         (NBUF + (REG ? 5 : 0)) * 1000000 + (SCR2 ? 100000 : 0) +
+         (TR % 100) * 1000 + MAXP * 10 + (GRAM ? NTB : 0);
   if constexpr (PC == 2)
-    hipLaunchKernelGGL((pass16_kernel<TR, NBUF, CAP, MAXP, GRAM, NTB, REG>),
-                       dim3((unsigned)G), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(
+        (pass16_kernel<T, TR, NBUF, CAP, MAXP, GRAM, NTB, REG>),
+        dim3((unsigned)G), dim3(256), 0, st, a);
   else
     hipLaunchKernelGGL(
-        (pass16_deep_kernel<TR, NBUF, CAP, NW, SCR2, MAXP, GRAM, NTB, REG>),
+        (pass16_deep_kernel<T, TR, NBUF, CAP, NW, SCR2, MAXP, GRAM, NTB, REG>),
         dim3((unsigned)G), dim3(NW * 64), 0, st, a);
   return hipGetLastError();
 }
@@ -549,37 +641,56 @@ static hipError_t go(const Args& a, int G, hipStream_t st, int* tag) {
 // partial-sum areas)
 struct Shape { int tr, nbuf, cap, per_cu, nw, scr2; };
 
-// launch_pass16 picks among these (or takes the tuned / BCGS_PASS16_SHAPE
-// index); its switch instantiates the same list, entry by entry.
-// Taller tiles stream faster (each copy instruction covers fewer columns,
-// so fewer pages and longer runs per column: on MI355X about 4.2, 5.7 and
-// 6.3 TB/s for 16, 32 and 64 rows), so wide passes take one workgroup of 8
-// waves per CU with 32- or 64-row tiles.  The last shape takes up to 544
-// columns (n up to 512 at s = 16) in one 8-wave workgroup per CU.
+// Binary64 shapes.  The launcher picks among these (or takes the tuned /
+// BCGS_PASS16_SHAPE index); dispatch() instantiates the same list, entry by
+// entry.  Taller tiles stream faster (each copy instruction covers fewer
+// columns, so fewer pages and longer runs per column: on MI355X about 4.2,
+// 5.7 and 6.3 TB/s for 16, 32 and 64 rows), so wide passes take one
+// workgroup of 8 waves per CU with 32- or 64-row tiles.  The last shape
+// takes up to 544 columns (n up to 512 at s = 16) in one 8-wave workgroup
+// per CU.
 constexpr Shape kShapes[] = {
     {64, 2, 64, 2, 4, 0},  {64, 2, 128, 1, 8, 0}, {32, 2, 272, 1, 8, 0},
     {32, 2, 128, 2, 4, 0}, {16, 2, 272, 2, 4, 0}, {16, 4, 272, 1, 4, 1},
     {16, 2, 544, 1, 8, 0}};
 constexpr int kNShapes = sizeof(kShapes) / sizeof(kShapes[0]);
 
-static int shape_maxp(const Shape& sh, int npairs) {
+// Binary32 shapes: the same bytes per column and tile as the 16-row
+// binary64 ones (32 rows of 4 bytes), so the same LDS budget.
+constexpr Shape kShapesF[] = {
+    {32, 2, 128, 2, 4, 0}, {32, 2, 272, 2, 4, 0}, {32, 2, 544, 1, 8, 0}};
+constexpr int kNShapesF = sizeof(kShapesF) / sizeof(kShapesF[0]);
+
+template <typename T> struct ShapeList;
+template <> struct ShapeList<double> {
+  static const Shape* get() { return kShapes; }
+  static constexpr int n = kNShapes;
+};
+template <> struct ShapeList<float> {
+  static const Shape* get() { return kShapesF; }
+  static constexpr int n = kNShapesF;
+};
+
+static inline int shape_maxp(const Shape& sh, int npairs) {
   return (npairs + sh.nw - 1) / sh.nw;
 }
 
+template <typename T>
 static bool shape_fits(const Shape& sh, int ncols_p, int shared_ksteps,
                        int npairs, bool reg) {
   if (reg && sh.nbuf != 2) return false;
   const int kg = sh.nw / (sh.tr / 16);
-  if ((shared_ksteps + kg - 1) / kg > kf_of(sh.cap)) return false;
+  if ((shared_ksteps + kg - 1) / kg > kf_of<T>(sh.cap)) return false;
   if (shape_maxp(sh, npairs) > 9) return false;
   return ncols_p <= sh.cap;
 }
 
-template <int TR, int NBUF, int CAP, int PC, int NW, bool SCR2, bool REG>
-static hipError_t go_shape(const Args& a, int G, bool gram, int ntb,
+template <typename T, int TR, int NBUF, int CAP, int PC, int NW, bool SCR2,
+          bool REG>
+static hipError_t go_shape(const ArgsT<T>& a, int G, bool gram, int ntb,
                            int maxp, hipStream_t st, int* tag) {
 #define GO(M_, G_, N_) \
-  go<TR, NBUF, CAP, PC, NW, SCR2, M_, G_, N_, REG>(a, G, st, tag)
+  go<T, TR, NBUF, CAP, PC, NW, SCR2, M_, G_, N_, REG>(a, G, st, tag)
   // largest pair count per wave this capacity can produce (two B blocks)
   constexpr int kTop = ((CAP / 16) * 2 + NW - 1) / NW;
   if (!gram) return GO(1, false, 1);
@@ -606,40 +717,125 @@ static hipError_t go_shape(const Args& a, int G, bool gram, int ntb,
 #undef GO
 }
 
-// Launch shape `pick` of kShapes (REG: register-staged tiles).
-// Instantiated in pass16.hip (REG = false) and pass16_reg.hip (REG = true).
-#define P16_DISPATCH_BODY(REG_)                                              \
-  switch (pick) {                                                            \
-    case 0: return go_shape<64, 2, 64, 2, 4, false, REG_>(a, G, gram, ntb,   \
-                                                          maxp, st, tag);    \
-    case 1: return go_shape<64, 2, 128, 1, 8, false, REG_>(a, G, gram, ntb,  \
-                                                           maxp, st, tag);   \
-    case 2: return go_shape<32, 2, 272, 1, 8, false, REG_>(a, G, gram, ntb,  \
-                                                           maxp, st, tag);   \
-    case 3: return go_shape<32, 2, 128, 2, 4, false, REG_>(a, G, gram, ntb,  \
-                                                           maxp, st, tag);   \
-    case 4: return go_shape<16, 2, 272, 2, 4, false, REG_>(a, G, gram, ntb,  \
-                                                           maxp, st, tag);   \
-    case 5:                                                                  \
-      if constexpr (!REG_)                                                   \
-        return go_shape<16, 4, 272, 1, 4, true, REG_>(a, G, gram, ntb, maxp, \
-                                                      st, tag);              \
-      return hipErrorNotSupported;                                           \
-    case 6: return go_shape<16, 2, 544, 1, 8, false, REG_>(a, G, gram, ntb,  \
-                                                           maxp, st, tag);   \
-  }                                                                          \
-  return hipErrorNotSupported;
-
-template <bool REG>
-hipError_t dispatch(int pick, const Args& a, int G, bool gram, int ntb,
+// Launch shape `pick` of the storage type's list (REG: register-staged
+// tiles).  Instantiated once per (T, REG) in pass16.hip, pass16_reg.hip and
+// pass16_f32.hip.
+template <typename T, bool REG>
+hipError_t dispatch(int pick, const ArgsT<T>& a, int G, bool gram, int ntb,
                     int maxp, hipStream_t st, int* tag) {
-  P16_DISPATCH_BODY(REG)
+#define GS(...) go_shape<T, __VA_ARGS__, REG>(a, G, gram, ntb, maxp, st, tag)
+  if constexpr (sizeof(T) == 8) {
+    switch (pick) {
+      case 0: return GS(64, 2, 64, 2, 4, false);
+      case 1: return GS(64, 2, 128, 1, 8, false);
+      case 2: return GS(32, 2, 272, 1, 8, false);
+      case 3: return GS(32, 2, 128, 2, 4, false);
+      case 4: return GS(16, 2, 272, 2, 4, false);
+      case 5:
+        if constexpr (!REG) return GS(16, 4, 272, 1, 4, true);
+        return hipErrorNotSupported;
+      case 6: return GS(16, 2, 544, 1, 8, false);
+    }
+  } else {
+    switch (pick) {
+      case 0: return GS(32, 2, 128, 2, 4, false);
+      case 1: return GS(32, 2, 272, 2, 4, false);
+      case 2: return GS(32, 2, 544, 1, 8, false);
+    }
+  }
+  return hipErrorNotSupported;
+#undef GS
 }
 
-extern template hipError_t dispatch<false>(int, const Args&, int, bool, int,
-                                           int, hipStream_t, int*);
-extern template hipError_t dispatch<true>(int, const Args&, int, bool, int,
-                                          int, hipStream_t, int*);
+#define P16_DISPATCH_DECL(T_, R_)                                          \
+  hipError_t dispatch<T_, R_>(int, const ArgsT<T_>&, int, bool, int, int, \
+                              hipStream_t, int*)
+extern template P16_DISPATCH_DECL(double, false);
+extern template P16_DISPATCH_DECL(double, true);
+extern template P16_DISPATCH_DECL(float, false);
+extern template P16_DISPATCH_DECL(float, true);
+
+// Shape choice and launch of one pass (hipErrorNotSupported, nothing
+// launched, when no shape of the list takes it).  *G_out receives the
+// number of workgroups used.
+template <typename T>
+hipError_t launch_pass16_t(const PassArgs<T>& pa, int64_t m,
+                           const Tuning& tune, hipStream_t st, int* tag,
+                           int* G_out) {
+  const Shape* shapes = ShapeList<T>::get();
+  constexpr int nshapes = ShapeList<T>::n;
+  const int s = pa.s;
+  if (pa.sp != 16 || s % 4 != 0) return hipErrorNotSupported;
+  if (pa.groups != 1) return hipErrorNotSupported;
+  if (pa.upd1 && pa.upd2 && pa.u2_c0 != pa.u1_c0 + s)
+    return hipErrorNotSupported;
+  auto al16 = [](const void* p) {
+    return (reinterpret_cast<uintptr_t>(p) & 15) == 0;
+  };
+  // direct copies need 16-byte aligned columns; otherwise the tiles are
+  // staged through registers
+  constexpr int E = kEpg<T>;
+  const bool dma = (pa.ldq % E == 0) && al16(pa.q) &&
+                   (!pa.fcols || (pa.ldf % E == 0 && al16(pa.f))) &&
+                   (!pa.ecols || (pa.lde % E == 0 && al16(pa.e)));
+  const bool reg = !dma;
+  const int nks1 = pa.upd1 ? (pa.u1_c0 + s) / 4 : 0;
+  const int nks2 = pa.upd2 ? pa.u2_c0 / 4 : 0;
+  const int shared = std::max(nks1, nks2);
+  const int ntb = pa.gram ? pa.gbn_p / 16 : 1;
+  if (ntb > 2) return hipErrorNotSupported;
+  const int npairs = pa.gram ? (pa.ga_p / 16) * ntb : 0;
+  int pick = -1;
+  int f = tune.shape;
+  if (f < 0 && sizeof(T) == 8) {
+    if (const char* env = getenv("BCGS_PASS16_SHAPE")) f = atoi(env);
+  }
+  if (f >= 0 && f < nshapes &&
+      shape_fits<T>(shapes[f], pa.ncols_p, shared, npairs, reg))
+    pick = f;
+  if constexpr (sizeof(T) == 8) {
+    // Automatic choice, measured on MI355X: passes with two B blocks of
+    // Gram (P-1S, P-2S) are bound by the MFMA work and run best with
+    // 16-row tiles, two workgroups per CU; the other wide passes are bound
+    // by the stream and take the 32-row, 8-wave shape.
+    static const int kHeavy[] = {0, 3, 4, 2, 5, 1, 6};
+    static const int kLight[] = {0, 3, 2, 4, 5, 1, 6};
+    static_assert(sizeof(kHeavy) / sizeof(int) == nshapes, "every shape");
+    const int* order = (pa.gram && ntb == 2) ? kHeavy : kLight;
+    for (int i = 0; pick < 0 && i < nshapes; ++i)
+      if (shape_fits<T>(shapes[order[i]], pa.ncols_p, shared, npairs, reg))
+        pick = order[i];
+  } else {
+    for (int i = 0; pick < 0 && i < nshapes; ++i)
+      if (shape_fits<T>(shapes[i], pa.ncols_p, shared, npairs, reg)) pick = i;
+  }
+  if (pick < 0) return hipErrorNotSupported;
+  const Shape sh = shapes[pick];
+  const int maxp = shape_maxp(sh, npairs);
+  ArgsT<T> a{};
+  // rows split over 256 * per_cu workgroups (256 CUs on MI355X), at most
+  // tune.max_wg of them
+  const int64_t rpw =
+      std::max(round_up64(cdiv(m, 256 * sh.per_cu), 64),
+               round_up64(cdiv(m, std::max(1, tune.max_wg)), 64));
+  const int G = (int)cdiv(m, rpw);
+  a.m = pa.m; a.s = s; a.ncols = pa.ncols; a.ncols_p = pa.ncols_p;
+  a.rows_per_wg = rpw;
+  a.q = pa.q; a.ldq = pa.ldq; a.nq = pa.nq;
+  a.f = pa.f; a.ldf = pa.ldf; a.fcols = pa.fcols;
+  a.e = pa.e; a.lde = pa.lde; a.ecols = pa.ecols;
+  a.upd1 = pa.upd1; a.u1_c0 = pa.u1_c0; a.c1 = pa.c1;
+  a.dst1 = pa.dst1; a.ldd1 = pa.ldd1;
+  a.upd2 = pa.upd2; a.u2_c0 = pa.u2_c0;
+  a.c2 = pa.c2; a.dst2 = pa.dst2; a.ldd2 = pa.ldd2;
+  a.gram = pa.gram; a.ga_p = pa.ga_p; a.gb0 = pa.gb0; a.gbn_p = pa.gbn_p;
+  a.skip_a0 = pa.skip_a0; a.skip_b1 = pa.skip_b1;
+  a.partial = pa.partial;
+  *G_out = G;
+  const bool gram = pa.gram;
+  return reg ? dispatch<T, true>(pick, a, G, gram, ntb, maxp, st, tag)
+             : dispatch<T, false>(pick, a, G, gram, ntb, maxp, st, tag);
+}
 
 }  // namespace p16
 }  // namespace bcgs

@@ -8,8 +8,7 @@
 namespace bcgs {
 namespace p16 {
 
-template hipError_t dispatch<true>(int, const Args&, int, bool, int, int,
-                                   hipStream_t, int*);
+template P16_DISPATCH_DECL(double, true);
 
 }  // namespace p16
 }  // namespace bcgs

@@ -75,3 +75,29 @@ def test_bulk32_bitwise_repeatable(variant):
     Q2, R2, _ = run_gpu(X, 16, variant, precision="fp32-bulk")
     assert np.array_equal(host(R1), host(R2))
     assert np.array_equal(host(Q1), host(Q2))
+
+
+@pytest.mark.parametrize("m,n", [(40000, 128), (40001, 256), (30000, 512)])
+def test_bulk32_fast_pass(m, n):
+    """s = 16 in binary32 runs the binary32 form of the s <= 16 pass (tag
+    digit W P with P >= 4), direct copies for aligned columns and register
+    staging for odd m; the result meets the FP32-bulk bounds."""
+    import torch
+    from paper_2507_21791_amd import bcgs
+    log(f"[gpu] fp32-bulk fast pass m={m} n={n}")
+    X = _fp32_input(m, n, 2, seed=m + n)
+    Xd = torch.empty((n, m), dtype=torch.float32, device="cuda").t()
+    Xd.copy_(torch.from_numpy(np.asfortranarray(X)).float())
+    ws = bcgs.Workspace(m, n, 16, "p-1s", "fp32-bulk")
+    stream = torch.cuda.current_stream()
+    bcgs.profile_start(stream)
+    Q, R, _ = bcgs.qr(Xd, 16, "p-1s", "fp32-bulk", ws=ws)
+    recs = bcgs.profile_stop(stream)
+    tags = [r["tag"] for r in recs if r["kind"] == "pass"]
+    assert tags and all(t >= 10 ** 9 and (t // 10 ** 7) % 10 >= 4
+                        for t in tags), tags
+    if m % 4:
+        assert all((t // 10 ** 6) % 10 >= 5 for t in tags), tags
+    out = compare_bulk32(X, 16, "p-1s", host(Q), host(R), ws.info(),
+                         kappa=1e2)
+    log("   ", out)
