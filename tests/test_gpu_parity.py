@@ -181,3 +181,40 @@ def test_fast_pass_takes_odd_rows_and_wide_blocks(m, n):
     if m % 2:
         assert all((t // 10 ** 6) % 10 >= 5 for t in tags), tags
     compare(X, 16, "p-1s", host(Q), host(R), ws.info(), kappa=1e3)
+
+
+@pytest.mark.parametrize("variant", ["p-1s", "bcgsi+"])
+def test_full_size_tall_properties_and_sampled_block(variant):
+    """The timed configuration itself (m = 2^22, n = 256, s = 16, launched
+    as bench.py launches it) on its kappa = 1e6 twin, where every variant's
+    Table 1 assumption holds: LOO and residual (FP64 chunked checker on the
+    device) within 10 n u, R exactly upper triangular with a positive
+    diagonal, and the sampled output R_11 (the TSQR of X_1) against the
+    oracle's Householder QR of that block on the host, within
+    10 sqrt(m) u kappa(X_1)."""
+    import torch
+    import bench
+    from paper_2507_21791_amd import bcgs
+    m, n, s = 1 << 22, 256, 16
+    log(f"[gpu] full size m={m} n={n} s={s} kappa=1e6 {variant}")
+    X = W.make_device("tall-k6")
+    torch.cuda.synchronize()
+    Q, R, ws = bcgs.qr(X, s, variant)
+    torch.cuda.synchronize()
+    info = ws.info()
+    assert info.status == 0, info.as_dict()
+    loo, res = bench.accuracy(X, Q, R)
+    u = 2.0 ** -53
+    assert loo <= 10 * n * u and res <= 10 * n * u, (loo, res)
+    Rh = R.cpu().numpy()
+    assert np.all(np.tril(Rh, -1) == 0.0) and np.all(np.diag(Rh) > 0)
+    X1 = np.asfortranarray(X[:, :s].cpu().numpy())
+    Q1o, R1o = O.FP64.qr_pos(X1)
+    err = np.linalg.norm(Rh[:s, :s] - R1o) / np.linalg.norm(R1o)
+    kappa1 = np.linalg.cond(R1o)
+    # both are backward-stable QRs of a 2^22-row block: typical rounding
+    # growth sqrt(m) u, times the block's condition number
+    assert err <= 10 * np.sqrt(m) * u * kappa1, (err, kappa1)
+    log(f"    loo={loo:.3g} res={res:.3g} R_11 err={err:.3g}")
+    del X, Q, R
+    torch.cuda.empty_cache()
