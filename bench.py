@@ -76,18 +76,40 @@ def time_variant(X, s, variant, steps, warmup, Q, R, precision="fp64"):
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
     bcgs.profile_start(stream)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    torch.cuda.synchronize()
+    ev[0].record(stream)
+    for k in range(steps):
+        bcgs.qr(X, s, variant, precision, Q=Q, R=R, ws=ws)
+        ev[k + 1].record(stream)
+    torch.cuda.synchronize()
+    recs = bcgs.profile_stop(stream)
+    ms = ev[0].elapsed_time(ev[steps]) / steps
+    per_step = [ev[k].elapsed_time(ev[k + 1]) for k in range(steps)]
+    info = ws.info()
+    time_variant.per_step = per_step
+    return ms, recs, info
+
+
+def copy_bandwidth(nbytes=1 << 31, reps=5):
+    """Measured device-to-device copy rate (bytes read + written per
+    second, GB/s): the practical streaming ceiling of this GPU."""
+    import torch
+    src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
-    e0.record(stream)
-    for _ in range(steps):
-        bcgs.qr(X, s, variant, precision, Q=Q, R=R, ws=ws)
-    e1.record(stream)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
     torch.cuda.synchronize()
-    recs = bcgs.profile_stop(stream)
-    ms = e0.elapsed_time(e1) / steps
-    info = ws.info()
-    return ms, recs, info
+    ms = e0.elapsed_time(e1) / reps
+    del src, dst
+    torch.cuda.empty_cache()
+    return 2.0 * nbytes / (ms * 1e-3) / 1e9
 
 
 def aggregate(recs, steps):
@@ -479,7 +501,11 @@ def main():
         agg = aggregate(recs, args.steps)
         model_bytes = sum(a["bytes"] for a in agg)
         model_flops = sum(a["flops"] for a in agg)
-        res = {"ms": round(ms, 4), "model_gb": round(model_bytes / 1e9, 3),
+        steps_ms = sorted(time_variant.per_step)
+        res = {"ms": round(ms, 4),
+               "step_ms_median": round(float(np.median(steps_ms)), 4),
+               "step_ms_p99": round(float(np.percentile(steps_ms, 99)), 4),
+               "model_gb": round(model_bytes / 1e9, 3),
                "gbs": round(model_bytes / (ms * 1e-3) / 1e9, 1),
                "tflops": round(model_flops / (ms * 1e-3) / 1e12, 2),
                "status": info.status, "syncs": info.syncs,
@@ -514,6 +540,7 @@ def main():
                                 f"{variants[0]}"),
                    "m": m, "n": n, "s": s, "variant": variants[0]},
         "hbm_frac": round(head["gbs"] / HBM_PEAK_GBS, 4),
+        "fp64_frac": round(head["tflops"] / FP64_PEAK_TFS, 4),
         "roofline": roofline(dom),
     }
     if "bcgsi+" in results and variants[0] != "bcgsi+":
@@ -530,6 +557,11 @@ def main():
     out["variants"] = {k: {kk: vv for kk, vv in r.items() if kk != "_agg"}
                        for k, r in results.items()}
     out["p99_latency_ms"] = None
+    cgbs = copy_bandwidth()
+    out["copy_gbs"] = round(cgbs, 1)
+    out["frac_of_copy"] = round(head["gbs"] / cgbs, 4)
+    log(f"[bench] device copy {cgbs:.1f} GB/s; P-1S at "
+        f"{head['gbs'] / cgbs:.3f} of it")
     rows = min(args.cpu_rows, m)
     Xhead = None if args.no_cpu else X[:rows].cpu()
     del X, Q, R
