@@ -364,15 +364,16 @@ def bench_served(nreq, rate, precision, pool, pool32, loo_every=50,
                  inflight=8, budget=96 << 30, arena=64 << 30):
     """Poisson arrivals at `rate` req/s of P-1S requests drawn from the
     device pool, through the library's request queue (continuous batching,
-    queue-allocated outputs).  Latency = completion - submission (the
-    submitter submits at each arrival time)."""
+    queue-allocated outputs, a request that breaks down rerun once as
+    P-2S).  Latency = completion - submission (the submitter submits at
+    each arrival time)."""
     import threading
     import torch
     from paper_2507_21791_amd import bcgs, workloads as W
     trace = W.served_trace(nreq, rate, len(pool))
     src = pool if precision == "fp64" else pool32
     q = bcgs.Queue(hbm_budget_bytes=budget, max_inflight=inflight,
-                   output_arena_bytes=arena)
+                   output_arena_bytes=arena, retry_variant="p-2s")
     tickets = [None] * nreq
     sampled = {}
 
@@ -414,6 +415,7 @@ def bench_served(nreq, rate, precision, pool, pool32, loo_every=50,
            "p50_ms": round(float(np.percentile(lat, 50)), 3),
            "p99_ms": round(float(np.percentile(lat, 99)), 3),
            "throughput_per_s": round(nreq / span, 1),
+           "retried_as_p2s": int(sum(1 for r in res if r["attempts"] > 1)),
            "breakdowns": int(sum(1 for r in res if r["status"] == 2)),
            "errors": int(sum(1 for r in res if r["status"] not in (0, 2))),
            "sampled_loo_max": max((l for l, _ in loos), default=None),

@@ -227,12 +227,16 @@ typedef struct {
     int32_t device;             /* HIP device ordinal */
     size_t output_arena_bytes;  /* device memory for queue-allocated Q and
                                    R (0: every request brings its own) */
+    int32_t retry_on_breakdown; /* nonzero: a request that breaks down runs
+                                   once more, first in line, with
+                                   retry_variant (same outputs) */
+    int32_t retry_variant;      /* bcgs_variant, e.g. BCGS_P_2S */
 } bcgs_queue_config;
 
 /* Outcome of one request; times are seconds on the host's steady clock
- * since the queue was created: submitted, admitted (work enqueued), and
- * found complete by the scheduler (which polls every ~20 us).  Q and R are
- * the queue-allocated outputs (ld = m and n), else NULL. */
+ * since the queue was created: submitted, first admitted (work enqueued),
+ * and found complete by the scheduler (which polls every ~20 us).  Q and R
+ * are the queue-allocated outputs (ld = m and n), else NULL. */
 typedef struct {
     bcgs_status status;       /* BCGS_PENDING, BCGS_OK, BCGS_ERR_BREAKDOWN,
                                  or the error that stopped the request */
@@ -240,6 +244,8 @@ typedef struct {
     double t_submit, t_start, t_done;
     void* Q;
     double* R;
+    int32_t variant;          /* variant of the run that produced the result */
+    int32_t attempts;         /* 1, or 2 after a retry on breakdown */
 } bcgs_request_stats;
 
 /* Create a queue (library streams, pinned info buffers, the output arena,

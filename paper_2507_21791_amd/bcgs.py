@@ -65,7 +65,9 @@ class QueueConfig(ctypes.Structure):
     """Mirror of bcgs_queue_config."""
     _fields_ = [("hbm_budget_bytes", ctypes.c_size_t),
                 ("max_inflight", ctypes.c_int32), ("device", ctypes.c_int32),
-                ("output_arena_bytes", ctypes.c_size_t)]
+                ("output_arena_bytes", ctypes.c_size_t),
+                ("retry_on_breakdown", ctypes.c_int32),
+                ("retry_variant", ctypes.c_int32)]
 
 
 class RequestStats(ctypes.Structure):
@@ -73,7 +75,8 @@ class RequestStats(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int), ("info", Info),
                 ("t_submit", ctypes.c_double), ("t_start", ctypes.c_double),
                 ("t_done", ctypes.c_double), ("Q", ctypes.c_void_p),
-                ("R", ctypes.c_void_p)]
+                ("R", ctypes.c_void_p), ("variant", ctypes.c_int32),
+                ("attempts", ctypes.c_int32)]
 
 
 _lib = None
@@ -351,10 +354,15 @@ class Queue:
     tensors of every request until it is collected."""
 
     def __init__(self, hbm_budget_bytes, max_inflight=8, device=0,
-                 output_arena_bytes=0):
+                 output_arena_bytes=0, retry_variant=None):
+        """retry_variant: variant name a request that breaks down is rerun
+        with once (e.g. "p-2s"), or None."""
         self.handle = ctypes.c_void_p()
         cfg = QueueConfig(int(hbm_budget_bytes), int(max_inflight),
-                          int(device), int(output_arena_bytes))
+                          int(device), int(output_arena_bytes),
+                          0 if retry_variant is None else 1,
+                          0 if retry_variant is None
+                          else VARIANTS[retry_variant])
         st = lib().bcgs_queue_create(ctypes.byref(cfg),
                                      ctypes.byref(self.handle))
         if st != BCGS_OK:
@@ -409,7 +417,9 @@ class Queue:
         X, Q, R, info = self.live.pop(ticket)
         return {"status": st, "info": out.info, "t_submit": out.t_submit,
                 "t_start": out.t_start, "t_done": out.t_done, "Q": Q, "R": R,
-                "Q_ptr": out.Q, "R_ptr": out.R}
+                "Q_ptr": out.Q, "R_ptr": out.R,
+                "variant": {v: k for k, v in VARIANTS.items()}[out.variant],
+                "attempts": out.attempts}
 
     def free(self, ptr, stream=None):
         """Return a queue-allocated Q or R to the arena once the work on

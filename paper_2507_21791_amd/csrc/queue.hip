@@ -14,6 +14,11 @@
 // times (host steady clock, seconds since the queue was created) are kept
 // until the caller collects them with poll or wait.
 //
+// Optionally a request whose Cholesky factorization breaks down is run
+// once more, at the head of the queue, with a more stable variant (e.g.
+// BCGSI+P-1S -> BCGSI+P-2S, whose Table 1 assumption is u kappa <= 1
+// instead of u kappa^2 <= 1), into the same outputs.
+//
 // A request may leave Q and R to the queue (both pointers NULL): they are
 // then carved at admission out of the queue's output arena (one device
 // allocation made when the queue is created; first-fit over 256-byte
@@ -47,6 +52,7 @@ struct Request {
   Plan plan;
   size_t footprint = 0;
   bool own = false;        // Q and R allocated by the queue at admission
+  bool placed = false;     // queue-allocated outputs already assigned
   bool done = false;
   bcgs_request_stats stats{};
 };
@@ -127,6 +133,8 @@ struct bcgs_queue {
   int device = 0;
   size_t budget = 0;
   size_t in_use = 0;
+  int retry = 0;                     // rerun breakdowns with retry_variant
+  int retry_variant = 0;
   std::chrono::steady_clock::time_point t0;
   std::mutex mu;
   std::condition_variable cv_work;   // scheduler: new request / stop
@@ -203,7 +211,8 @@ void bcgs_queue::run() {
       if (!sl.ticket) continue;
       const hipError_t q = hipEventQuery(sl.done);
       if (q == hipErrorNotReady) continue;
-      Request& rq = reqs[sl.ticket];
+      const uint64_t tk = sl.ticket;
+      Request& rq = reqs[tk];
       rq.stats.t_done = now();
       if (q == hipSuccess) {
         rq.stats.info = *sl.host_info;
@@ -213,10 +222,26 @@ void bcgs_queue::run() {
         rq.stats.status = BCGS_ERR_HIP;
         fault = BCGS_ERR_HIP;
       }
-      rq.done = true;
       in_use -= rq.footprint;
       --running;
       sl.ticket = 0;
+      Plan again;
+      if (rq.stats.status == BCGS_ERR_BREAKDOWN && retry &&
+          rq.stats.attempts == 1 && rq.prob.variant != retry_variant &&
+          check_problem(rq.prob.X, rq.prob.ldx, rq.prob.m, rq.prob.n,
+                        rq.prob.s, retry_variant, rq.prob.precision,
+                        rq.prob.Q, rq.prob.ldq, rq.prob.R, rq.prob.ldr,
+                        rq.prob.d_info, &again) == BCGS_OK) {
+        // run it once more, first in line, with the stable variant
+        rq.prob.variant = retry_variant;
+        rq.plan = again;
+        rq.footprint = footprint_of(rq.prob, again);
+        rq.stats.variant = retry_variant;
+        rq.stats.status = BCGS_PENDING;
+        waiting.push_front(tk);
+        continue;
+      }
+      rq.done = true;
       cv_done.notify_all();
     }
     // 2. admit in arrival order while a slot and the memory are free
@@ -234,7 +259,7 @@ void bcgs_queue::run() {
     while (!waiting.empty() && running < nslots) {
       Request& rq = reqs[waiting.front()];
       if (running > 0 && in_use + rq.footprint > budget) break;
-      if (rq.own) {
+      if (rq.own && !rq.placed) {
         // outputs from the arena: Q then R, both or neither
         const size_t oq = out.alloc(q_bytes(rq.prob));
         const size_t orr = oq == SIZE_MAX ? SIZE_MAX : out.alloc(r_bytes(rq.prob));
@@ -256,7 +281,9 @@ void bcgs_queue::run() {
         rq.prob.R = reinterpret_cast<double*>(out_base + orr);
         rq.stats.Q = rq.prob.Q;
         rq.stats.R = rq.prob.R;
+        rq.placed = true;
       }
+      ++rq.stats.attempts;
       int k = 0;
       while (slots[k].ticket) ++k;
       const uint64_t t = waiting.front();
@@ -311,6 +338,9 @@ bcgs_status bcgs_queue_create(const bcgs_queue_config* cfg,
   if (cfg->max_inflight < 1 || cfg->max_inflight > kMaxSlots ||
       cfg->hbm_budget_bytes == 0)
     return BCGS_ERR_ARG;
+  if (cfg->retry_on_breakdown &&
+      (cfg->retry_variant < BCGS_I_PLUS || cfg->retry_variant > BCGS_I_PLUS_1S))
+    return BCGS_ERR_ARG;
   const size_t arena = cfg->output_arena_bytes & ~size_t(255);
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess) return BCGS_ERR_HIP;
@@ -319,6 +349,8 @@ bcgs_status bcgs_queue_create(const bcgs_queue_config* cfg,
   q->device = cfg->device;
   q->budget = cfg->hbm_budget_bytes;
   q->nslots = cfg->max_inflight;
+  q->retry = cfg->retry_on_breakdown != 0;
+  q->retry_variant = cfg->retry_variant;
   q->t0 = std::chrono::steady_clock::now();
   int prev = 0;
   (void)hipGetDevice(&prev);
@@ -391,6 +423,8 @@ bcgs_status bcgs_queue_submit(bcgs_queue_t q, const bcgs_problem* p,
   if (q->fault != BCGS_OK) return q->fault;
   if (q->waiting.size() >= kMaxWaiting) return BCGS_ERR_QUEUE_FULL;
   rq.stats.status = BCGS_PENDING;
+  rq.stats.variant = p->variant;
+  rq.stats.attempts = 0;
   rq.stats.t_submit = q->now();
   const uint64_t t = q->next_ticket++;
   q->reqs.emplace(t, rq);

@@ -167,19 +167,22 @@ def test_tuning_table():
 
 
 def test_queue_struct_layouts():
-    assert ctypes.sizeof(bcgs.QueueConfig) == 24
+    assert ctypes.sizeof(bcgs.QueueConfig) == 32
     assert bcgs.QueueConfig.output_arena_bytes.offset == 16
-    assert ctypes.sizeof(bcgs.RequestStats) == 80
+    assert bcgs.QueueConfig.retry_variant.offset == 28
+    assert ctypes.sizeof(bcgs.RequestStats) == 88
     assert bcgs.RequestStats.info.offset == 8
     assert bcgs.RequestStats.t_done.offset == 56
     assert bcgs.RequestStats.R.offset == 72
+    assert bcgs.RequestStats.attempts.offset == 84
 
 
-@pytest.mark.parametrize("budget,inflight", [(0, 4), (1 << 30, 0),
-                                             (1 << 30, 17)])
-def test_queue_bad_config_rejected(budget, inflight):
+@pytest.mark.parametrize("budget,inflight,retry", [
+    (0, 4, (0, 0)), (1 << 30, 0, (0, 0)), (1 << 30, 17, (0, 0)),
+    (1 << 30, 4, (1, 9))])
+def test_queue_bad_config_rejected(budget, inflight, retry):
     L = bcgs.lib()
-    cfg = bcgs.QueueConfig(budget, inflight, 0)
+    cfg = bcgs.QueueConfig(budget, inflight, 0, 0, *retry)
     h = ctypes.c_void_p()
     assert L.bcgs_queue_create(ctypes.byref(cfg), ctypes.byref(h)) == \
         bcgs.BCGS_ERR_ARG

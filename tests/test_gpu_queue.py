@@ -255,3 +255,44 @@ def test_queue_arena_space_gates_admission():
     finally:
         q.close()
     assert not _overlaps(res)
+
+
+def test_queue_retries_breakdown_with_stable_variant():
+    """kappa = 1e12: BCGSI+P-1S breaks down (u kappa^2 >> 1) while
+    BCGSI+P-2S holds O(u) orthogonality (u kappa <= 1, Table 1).  With
+    retry enabled the request is rerun once as P-2S into the same outputs:
+    status ok, variant p-2s, two attempts, the bits of a lone P-2S run and
+    the oracle's P-2S tolerances; without retry it reports the breakdown."""
+    import torch
+    from paper_2507_21791_amd import bcgs
+    log("[gpu] queue retry on breakdown")
+    X = W.conditioned_host(3000, 64, 12, seed=1)
+    Xd = to_device(X, torch.float64)
+    want = O.qr(X, 16, "p-1s").breakdown
+    assert want is not None
+    q = bcgs.Queue(hbm_budget_bytes=8 << 30, max_inflight=2,
+                   output_arena_bytes=64 << 20, retry_variant="p-2s")
+    q0 = bcgs.Queue(hbm_budget_bytes=8 << 30, max_inflight=2)
+    try:
+        t = q.submit(Xd, 16, "p-1s")
+        r = q.wait(t)
+        tq = q.submit(Xd, 16, "p-1s", outputs="queue")
+        rq = q.wait(tq)
+        r0 = q0.wait(q0.submit(Xd, 16, "p-1s"))
+        assert rq["status"] == 0 and rq["attempts"] == 2
+        Qq = _copy_out(rq["Q_ptr"], 3000, 64, np.float64)
+        q.free(rq["Q_ptr"])
+        q.free(rq["R_ptr"])
+    finally:
+        q.close()
+        q0.close()
+    assert r0["status"] == bcgs.BCGS_ERR_BREAKDOWN and r0["attempts"] == 1
+    # far past Table 1's assumption the failing pivot is a rounding-order
+    # matter; the failing block is the parity criterion
+    assert r0["info"].block == want.block, (r0["info"].as_dict(), want)
+    assert r["status"] == 0 and r["variant"] == "p-2s" and r["attempts"] == 2
+    Qa, Ra, _ = _alone(Xd, 16, "p-2s", "fp64")
+    assert np.array_equal(host(r["R"]), Ra)
+    assert np.array_equal(host(r["Q"]), Qa)
+    assert np.array_equal(Qq, Qa)
+    compare(X, 16, "p-2s", host(r["Q"]), host(r["R"]), r["info"], kappa=1e12)
