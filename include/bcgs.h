@@ -171,7 +171,8 @@ typedef struct {
  * of bcgs_qr_ex, BCGS_ERR_NOMEM if the arena cannot grow, BCGS_ERR_HIP on a
  * runtime failure, BCGS_OK otherwise (count == 0 enqueues nothing).
  * Environment BCGS_BATCH_MODE=streams enqueues the same branches directly,
- * without the graph (for comparison). */
+ * without the graph (for comparison); BCGS_BATCH_BRANCHES (1..16, default
+ * 8) sets the number of branch streams. */
 bcgs_status bcgs_qr_batched(const bcgs_problem* probs, int32_t count,
                             hipStream_t stream);
 

@@ -96,7 +96,17 @@ static double model_cost(const bcgs_problem& p) {
 // --------------------------------------------------------- batch state ---
 namespace {
 
-constexpr int kBranches = 8;
+constexpr int kBranches = 16;          // streams created per caller stream
+
+// branches used by a batch: BCGS_BATCH_BRANCHES (1..16), default 8
+int branches_used() {
+  static const int n = [] {
+    const char* e = getenv("BCGS_BATCH_BRANCHES");
+    const int v = e ? atoi(e) : 8;
+    return v < 1 ? 1 : (v > kBranches ? kBranches : v);
+  }();
+  return n;
+}
 
 struct BatchState {
   int device = -1;
@@ -203,9 +213,10 @@ bcgs_status bcgs_qr_batched(const bcgs_problem* probs, int32_t count,
   });
   {
     double load[kBranches] = {};
+    const int nb = branches_used();
     for (int i : order) {
       int k = 0;
-      for (int j = 1; j < kBranches; ++j)
+      for (int j = 1; j < nb; ++j)
         if (load[j] < load[k]) k = j;
       branch_of[i] = k;
       load[k] += model_cost(probs[i]);
