@@ -23,6 +23,10 @@ struct EpiSmem {
   double A[kMaxS * kMaxS];     // matrix being factored (row-major s x s)
   double B[kMaxS * kMaxS];     // scratch s x s
   double P[256];               // 16 x 16 right operand of mm16
+  // s <= 16, one-sync epilogue: the factors stay in LDS for the
+  // coefficient matrices (all s x s row-major, stride s)
+  double T1[256], T2[256], T1i[256], T2i[256], L[256], N[256];
+  double P2[512];              // 32 x 16 right operand of mmk<32>
   double bc[4];
   int flag;
 };
@@ -132,11 +136,11 @@ __device__ __forceinline__ void chol(EpiSmem& sm, int s, bcgs_info* info,
 }
 
 // T^{-1} of the upper triangular s x s matrix T (row-major, LDS) into Ti:
-// lane j of wave 0 forms column j by back substitution in registers.
+// lane j of wave `w` forms column j by back substitution in registers.
 template <int S>
-__device__ void tri_inv_wave(const double* T, double* Ti) {
-  if (threadIdx.x < 64) {
-    const int j = threadIdx.x;
+__device__ void tri_inv_wave(const double* T, double* Ti, int w = 0) {
+  if ((threadIdx.x >> 6) == w) {
+    const int j = threadIdx.x & 63;
     double x[S];
 #pragma unroll
     for (int i = S - 1; i >= 0; --i) {
@@ -166,7 +170,7 @@ __device__ __forceinline__ double gram_at(const EpiArgs& a, int r, int c) {
 template <int S, class FA, class FO>
 __device__ __forceinline__ void mm16(int rows, FA a_at, const double* P,
                                      FO out) {
-  static_assert(S == 4 || S == 8 || S == 16, "16x16x4 blocks");
+  static_assert(S % 4 == 0 && S <= 32, "whole 16x16x4 K-steps");
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int li = lane & 15, lk = lane >> 4;
   for (int rb = wave; rb * 16 < rows; rb += kWaves) {
@@ -256,6 +260,85 @@ __device__ void gram_products(const EpiArgs& a, int js, bool has_e,
   __syncthreads();
 }
 
+// Coefficient matrices of the one-sync epilogue for s = S <= 16, from
+// LDS-resident factors (no round trip through the global copies written
+// by the same kernel):
+//   F1 = [-Y T1^{-1}; T1^{-1}]   (Y = Gram rows [0, js), columns [0, S))
+// and, when the next pass also forms U_{j+1}, F2 with F1 folded in
+// (fold_coefs): with M = -L T2^{-1} and N = T1^{-1} M,
+//   F2'(0:js)       = Z (-T2^{-1}) + Y (-N)   (one product of K = 2S)
+//   F2'(js:js+S)    = N
+//   F2'(js+S:js+2S) = T2^{-1}
+// where T2 = S_{j+1,j+1} (scaled) or I, Z = Gram columns [S, 2S).
+template <int S>
+__device__ void coefs_fused(EpiSmem& sm, const EpiArgs& a, int js) {
+  const int tid = threadIdx.x;
+  const bool two = a.f2_mode != COEF_NONE;
+  const bool scaled2 = a.f2_mode == COEF_SCALED;
+  __syncthreads();
+  tri_inv_wave<S>(sm.T1, sm.T1i, 0);
+  if (two && scaled2) {
+    tri_inv_wave<S>(sm.T2, sm.T2i, 1);
+  } else if (two) {
+    for (int e = tid; e < S * S; e += kThreads)
+      sm.T2i[e] = (e / S == e % S) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  // F1 rows [0, js): -Y T1^{-1}; rows [js, js+S): T1^{-1}
+  for (int e = tid; e < 256; e += kThreads) {
+    const int k = e >> 4, c = e & 15;
+    sm.P[e] = (k < S && c < S) ? -sm.T1i[k * S + c] : 0.0;
+  }
+  if (two) {
+    // M = -L T2^{-1} into sm.N for now (T2^{-1} upper triangular)
+    if (tid < S * S) {
+      const int x = tid / S, y = tid % S;
+      double acc = 0.0;
+#pragma unroll
+      for (int k = 0; k < S; ++k) acc -= sm.L[x * S + k] * sm.T2i[k * S + y];
+      sm.A[tid] = acc;
+    }
+  }
+  __syncthreads();
+  mm16<S>(
+      js, [&](int i, int k) { return gram_at(a, i, k); }, sm.P,
+      [&](int i, int c, double v) { a.f1[(size_t)i * 16 + c] = v; });
+  for (int e = tid; e < S * 16; e += kThreads) {
+    const int i = e / 16, c = e % 16;
+    a.f1[(size_t)(js + i) * 16 + c] = c < S ? sm.T1i[i * S + c] : 0.0;
+  }
+  if (!two) return;
+  // N = T1^{-1} M (T1^{-1} upper triangular)
+  if (tid < S * S) {
+    const int x = tid / S, y = tid % S;
+    double acc = 0.0;
+#pragma unroll
+    for (int k = 0; k < S; ++k) acc += sm.T1i[x * S + k] * sm.A[k * S + y];
+    sm.N[tid] = acc;
+  }
+  __syncthreads();
+  // right operand [-T2^{-1}; -N] (2S x 16, zero beyond S columns)
+  for (int e = tid; e < 2 * S * 16; e += kThreads) {
+    const int k = e >> 4, c = e & 15;
+    double v = 0.0;
+    if (c < S) v = k < S ? -sm.T2i[k * S + c] : -sm.N[(k - S) * S + c];
+    sm.P2[e] = v;
+  }
+  __syncthreads();
+  mm16<2 * S>(
+      js,
+      [&](int i, int k) {
+        return k < S ? gram_at(a, i, S + k) : gram_at(a, i, k - S);
+      },
+      sm.P2, [&](int i, int c, double v) { a.f2[(size_t)i * 16 + c] = v; });
+  for (int e = tid; e < 2 * S * 16; e += kThreads) {
+    const int i = e / 16, c = e % 16;
+    double v = 0.0;
+    if (c < S) v = i < S ? sm.N[i * S + c] : sm.T2i[(i - S) * S + c];
+    a.f2[(size_t)(js + i) * 16 + c] = v;
+  }
+}
+
 __device__ void store_identity(double* dst, int sp, int s) {
   for (int e = threadIdx.x; e < sp * sp; e += kThreads) {
     const int i = e / sp, l = e % sp;
@@ -277,7 +360,7 @@ __device__ void store_tri(double* dst, int sp, int s, const double* src) {
 template <int S>
 __device__ void assemble_r(EpiSmem& sm, const EpiArgs& a, const double* c1,
                            const double* c2, const double* T1,
-                           const double* t2) {
+                           const double* t2, bool c1_is_gram = false) {
   const int s = S ? S : a.s, sp = a.sp, js = a.j * s;
   double* T2 = sm.B;
   __syncthreads();
@@ -288,7 +371,11 @@ __device__ void assemble_r(EpiSmem& sm, const EpiArgs& a, const double* c1,
     load_p<S>(sm, T2, S);
     __syncthreads();
     mm16<S>(
-        js, [&](int i, int k) { return c1[(size_t)i * sp + k]; }, sm.P,
+        js,
+        [&](int i, int k) {
+          return c1_is_gram ? gram_at(a, i, k) : c1[(size_t)i * sp + k];
+        },
+        sm.P,
         [&](int i, int c, double v) {
           if (c < S)
             a.r[(size_t)(js + c) * a.ldr + i] = v + c2[(size_t)i * sp + c];
@@ -453,17 +540,18 @@ __device__ void make_coefs(EpiSmem& sm, const EpiArgs& a) {
 }
 
 template <int S>
-__device__ void epilogue_body(EpiArgs a, EpiSmem& sm);
+__device__ bool epilogue_body(EpiArgs a, EpiSmem& sm);
 
 template <int S>
 __global__ __launch_bounds__(kThreads) void epilogue_kernel(EpiArgs a) {
   __shared__ EpiSmem sm;
-  epilogue_body<S>(a, sm);
-  make_coefs<S>(sm, a);
+  if (!epilogue_body<S>(a, sm)) make_coefs<S>(sm, a);
 }
 
+// Returns true when it has also written the coefficient matrices.
 template <int S>
-__device__ void epilogue_body(EpiArgs a, EpiSmem& sm) {
+__device__ bool epilogue_body(EpiArgs a, EpiSmem& sm) {
+  constexpr bool kFast = S == 4 || S == 8 || S == 16;
   const int tid = threadIdx.x;
   const int s = S ? S : a.s, sp = a.sp, js = a.j * s;
 
@@ -474,14 +562,14 @@ __device__ void epilogue_body(EpiArgs a, EpiSmem& sm) {
       dst[e] = c < s ? gram_at(a, i, c) : 0.0;
     }
     if (a.unit_s) store_identity(a.t2, sp, s);
-    return;
+    return false;
   }
 
   if (a.mode == EPI_R_ASSEMBLE) {
     for (int e = tid; e < s * s; e += kThreads)
       sm.A[e] = a.t1[(e / s) * sp + e % s];
     assemble_r<S>(sm, a, a.c1, a.c2, sm.A, a.t2);
-    return;
+    return false;
   }
 
   if (a.mode == EPI_S_CHOL) {
@@ -507,7 +595,7 @@ __device__ void epilogue_body(EpiArgs a, EpiSmem& sm) {
     __syncthreads();
     chol<S>(sm, s, a.info, a.j, 0);
     store_tri(a.t2, sp, s, sm.A);
-    return;
+    return false;
   }
 
   // EPI_ONE_SYNC, after [Q_{0:j-1} U_j (E)]^T [U_j (E)]:
@@ -562,15 +650,26 @@ __device__ void epilogue_body(EpiArgs a, EpiSmem& sm) {
   __syncthreads();
   chol<S>(sm, s, a.info, a.j, 1);
   // 2. R block column j with the current S (C2, T2) and the new Y, Y_jj
-  //    (C1/T1 are overwritten below, so write the new Y into C1 first)
-  for (int e = tid; e < js * sp; e += kThreads) {
-    const int i = e / sp, c = e % sp;
-    a.c1[e] = c < s ? gram_at(a, i, c) : 0.0;
+  //    (C1/T1 are overwritten below, so write the new Y into C1 first;
+  //    the s <= 16 path reads Y from the Gram and keeps Y_jj in LDS)
+  if constexpr (kFast) {
+    if (tid < S * S) sm.T1[tid] = sm.A[tid];
+  } else {
+    for (int e = tid; e < js * sp; e += kThreads) {
+      const int i = e / sp, c = e % sp;
+      a.c1[e] = c < s ? gram_at(a, i, c) : 0.0;
+    }
   }
   store_tri(a.t1, sp, s, sm.A);
   __syncthreads();
-  assemble_r<S>(sm, a, a.c1, a.c2, sm.A, a.t2);
-  if (!a.has_e) return;
+  assemble_r<S>(sm, a, a.c1, a.c2, sm.A, a.t2, kFast);
+  if (!a.has_e) {
+    if constexpr (kFast) {
+      coefs_fused<S>(sm, a, js);
+      return true;
+    }
+    return false;
+  }
   // 3. eq. (1): lower block L = Y_jj^{-T} (P - Y^T Z), forward substitution
   //    with Y_jj^T (lower triangular), one column per thread
 #pragma unroll
@@ -602,6 +701,9 @@ __device__ void epilogue_body(EpiArgs a, EpiSmem& sm) {
     }
   }
   __syncthreads();
+  if constexpr (kFast) {
+    if (tid < S * S) sm.L[tid] = sm.B[tid];
+  }
   // C2 <- [Z; L]
   for (int e = tid; e < (js + s) * sp; e += kThreads) {
     const int i = e / sp, c = e % sp;
@@ -611,9 +713,14 @@ __device__ void epilogue_body(EpiArgs a, EpiSmem& sm) {
   }
   if (a.unit_s) {                     // BCGSI+1s: S_{j+1,j+1} = I
     store_identity(a.t2, sp, s);
-    return;
   }
-  if (!a.chol_s) return;
+  if (a.unit_s || !a.chol_s) {
+    if constexpr (kFast) {
+      coefs_fused<S>(sm, a, js);
+      return true;
+    }
+    return false;
+  }
   // 4. S_{j+1,j+1} = chol(T - S^T S) with S = [Z; L]
   double tmp[kPer];
 #pragma unroll
@@ -635,6 +742,12 @@ __device__ void epilogue_body(EpiArgs a, EpiSmem& sm) {
   __syncthreads();
   chol<S>(sm, s, a.info, a.j + 1, 0);
   store_tri(a.t2, sp, s, sm.A);
+  if constexpr (kFast) {
+    if (tid < S * S) sm.T2[tid] = sm.A[tid];
+    coefs_fused<S>(sm, a, js);
+    return true;
+  }
+  return false;
 }
 
 hipError_t launch_epilogue(const EpiArgs& a, hipStream_t st) {
