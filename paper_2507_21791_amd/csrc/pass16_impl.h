@@ -115,6 +115,7 @@ struct ArgsT {
   int64_t m;
   int s, ncols, ncols_p;
   int64_t rows_per_wg;
+  int interleave;        // tiles dealt round-robin to the workgroups
   const T* q; int64_t ldq; int nq;
   const T* f; int64_t ldf; int fcols;
   const T* e; int64_t lde; int ecols;
@@ -289,28 +290,32 @@ struct Kernel {
                                                  int64_t r0, int rows) {
     const int lane = threadIdx.x & 63;
     const int li = lane & 15, lk = lane >> 4;
-    // K-steps in uniform chunks of 4; inside a chunk the four fragment
-    // loads are issued first; K-steps past ke read a valid address and
-    // meet zero coefficient fragments, so no lane-divergent branches
+    // K-steps in chunks of CH, the CH fragment loads of a chunk issued
+    // first; a step past ke reads a valid address and meets a zero
+    // coefficient fragment, so a wave runs its ke - kb steps rounded up to
+    // a multiple of CH with no branch inside a chunk.  Chunks of 2 waste
+    // fewer MFMAs; register-staged tiles (more registers live) keep
+    // chunks of 4, which the compiler fits with fewer spills.
+    constexpr int CH = REG ? 4 : 2;
     Acc acc1 = {0, 0, 0, 0}, acc2 = {0, 0, 0, 0};
     Acc acc1b = {0, 0, 0, 0}, acc2b = {0, 0, 0, 0};
     const int kcl = max(S.kb, S.ke - 1);
     const int row = S.mb * 16 + li;
 #pragma unroll
-    for (int q = 0; q < KF / 4; ++q) {
-      if (4 * q >= S.ke - S.kb) break;
-      T av[4];
+    for (int q = 0; q < KF / CH; ++q) {
+      if (CH * q >= S.ke - S.kb) break;           // wave-uniform
+      T av[CH];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int k = min(S.kb + 4 * q + u, kcl);
+      for (int u = 0; u < CH; ++u) {
+        const int k = min(S.kb + CH * q + u, kcl);
         av[u] = tile[at<T, TR>(4 * k + lk, row)];
       }
 #pragma unroll
-      for (int u = 0; u < 4; u += 2) {
-        if (U1) acc1 = mfma16(av[u], S.c1f[4 * q + u], acc1);
-        if (U2) acc2 = mfma16(av[u], S.c2f[4 * q + u], acc2);
-        if (U1) acc1b = mfma16(av[u + 1], S.c1f[4 * q + u + 1], acc1b);
-        if (U2) acc2b = mfma16(av[u + 1], S.c2f[4 * q + u + 1], acc2b);
+      for (int u = 0; u < CH; u += 2) {
+        if (U1) acc1 = mfma16(av[u], S.c1f[CH * q + u], acc1);
+        if (U2) acc2 = mfma16(av[u], S.c2f[CH * q + u], acc2);
+        if (U1) acc1b = mfma16(av[u + 1], S.c1f[CH * q + u + 1], acc1b);
+        if (U2) acc2b = mfma16(av[u + 1], S.c2f[CH * q + u + 1], acc2b);
       }
     }
     if (U2) {
@@ -438,11 +443,11 @@ struct Kernel {
   static __device__ __forceinline__ void step(const Args& a, State& S,
                                               T* const (&bufs)[4],
                                               T* scr, int64_t row0,
-                                              int64_t t) {
+                                              int64_t ts, int64_t t) {
     __builtin_amdgcn_s_waitcnt(P16_VM((NBUF - 2) * IPW));
     lds_barrier();
-    dma(a, bufs[(I + NBUF - 1) % NBUF], row0 + (t + NBUF - 1) * TR);
-    process(a, S, bufs[I], scr, row0 + t * TR, TR);
+    dma(a, bufs[(I + NBUF - 1) % NBUF], row0 + (t + NBUF - 1) * ts);
+    process(a, S, bufs[I], scr, row0 + t * ts, TR);
   }
 
   // register-staged step on buffer I: tile t is in buffer I and tile t+1
@@ -452,11 +457,12 @@ struct Kernel {
   static __device__ __forceinline__ void step_reg(const Args& a, State& S,
                                                   T* const (&bufs)[4],
                                                   T* scr, int64_t row0,
-                                                  int64_t t, int64_t nfull,
+                                                  int64_t ts, int64_t t,
+                                                  int64_t nfull,
                                                   V16 (&pend)[IPW]) {
-    process(a, S, bufs[I], scr, row0 + t * TR, TR);
+    process(a, S, bufs[I], scr, row0 + t * ts, TR);
     if (t + 1 < nfull) commit(a, bufs[I ^ 1], pend);
-    if (t + 2 < nfull) issue(a, row0 + (t + 2) * TR, pend);
+    if (t + 2 < nfull) issue(a, row0 + (t + 2) * ts, pend);
     lds_barrier();
   }
 
@@ -471,8 +477,28 @@ struct Kernel {
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform
     const int li = lane & 15, lk = lane >> 4;
     const int64_t g = blockIdx.x;
-    const int64_t row_begin = g * a.rows_per_wg;
-    const int64_t row_end = min(a.m, row_begin + a.rows_per_wg);
+    // Tiles of this workgroup: nfull full tiles at rows row_begin + t ts,
+    // then possibly one short tile of rows [rt, rt_end).  Contiguous: a
+    // range of rows_per_wg rows per workgroup.  Interleaved: full tile i of
+    // the matrix goes to workgroup i mod G (the short last tile too), so
+    // the workgroups running together read one narrow band of rows of
+    // every column.
+    int64_t row_begin, ts, nfull, rt, rt_end;
+    if (a.interleave) {
+      const int64_t G = gridDim.x, nt = a.m / TR;
+      row_begin = g * TR;
+      ts = G * TR;
+      nfull = nt > g ? (nt - g + G - 1) / G : 0;
+      rt = nt * TR;
+      rt_end = (nt % G == g) ? a.m : rt;
+    } else {
+      row_begin = g * a.rows_per_wg;
+      const int64_t row_end = min(a.m, row_begin + a.rows_per_wg);
+      ts = TR;
+      nfull = row_end > row_begin ? (row_end - row_begin) / TR : 0;
+      rt = row_begin + nfull * TR;
+      rt_end = max(rt, row_end);
+    }
 
     State S;
     S.mb = wave % MB;
@@ -522,7 +548,6 @@ struct Kernel {
     }
 
     // ---- full tiles ----
-    const int64_t nfull = row_end > row_begin ? (row_end - row_begin) / TR : 0;
     int64_t t = 0, issued = 0;
     if constexpr (REG) {
       static_assert(NBUF == 2, "register staging uses two buffers");
@@ -531,26 +556,26 @@ struct Kernel {
         issue(a, row_begin, pend);
         commit(a, b0, pend);
       }
-      if (nfull >= 2) issue(a, row_begin + TR, pend);
+      if (nfull >= 2) issue(a, row_begin + ts, pend);
       lds_barrier();
       for (; t + 1 < nfull; t += 2) {
-        step_reg<0>(a, S, bufs, scr, row_begin, t, nfull, pend);
-        step_reg<1>(a, S, bufs, scr, row_begin, t + 1, nfull, pend);
+        step_reg<0>(a, S, bufs, scr, row_begin, ts, t, nfull, pend);
+        step_reg<1>(a, S, bufs, scr, row_begin, ts, t + 1, nfull, pend);
       }
       if (t < nfull) {
-        step_reg<0>(a, S, bufs, scr, row_begin, t, nfull, pend);
+        step_reg<0>(a, S, bufs, scr, row_begin, ts, t, nfull, pend);
         ++t;
       }
       issued = nfull;
     } else if (nfull >= 2 * NBUF - 1) {
 #pragma unroll
       for (int i = 0; i < NBUF - 1; ++i)
-        dma(a, bufs[i], row_begin + i * TR);
+        dma(a, bufs[i], row_begin + i * ts);
       for (; t + 2 * NBUF - 2 < nfull; t += NBUF) {
-        step<0>(a, S, bufs, scr, row_begin, t);
-        step<1>(a, S, bufs, scr, row_begin, t + 1);
-        if constexpr (NBUF > 2) step<2>(a, S, bufs, scr, row_begin, t + 2);
-        if constexpr (NBUF > 3) step<3>(a, S, bufs, scr, row_begin, t + 3);
+        step<0>(a, S, bufs, scr, row_begin, ts, t);
+        step<1>(a, S, bufs, scr, row_begin, ts, t + 1);
+        if constexpr (NBUF > 2) step<2>(a, S, bufs, scr, row_begin, ts, t + 2);
+        if constexpr (NBUF > 3) step<3>(a, S, bufs, scr, row_begin, ts, t + 3);
       }
       issued = t + NBUF - 1;
     }
@@ -558,19 +583,18 @@ struct Kernel {
     for (; t < nfull; ++t) {
       const int bi = (int)(t % NBUF);
       T* tile = bi == 0 ? b0 : bi == 1 ? b1 : bi == 2 ? b2 : b3;
-      if (t >= issued) dma(a, tile, row_begin + t * TR);
+      if (t >= issued) dma(a, tile, row_begin + t * ts);
       __builtin_amdgcn_s_waitcnt(0);
       lds_barrier();
-      process(a, S, tile, scr, row_begin + t * TR, TR);
+      process(a, S, tile, scr, row_begin + t * ts, TR);
     }
     // ---- short last tile ----
-    const int64_t rt = row_begin + nfull * TR;
-    if (rt < row_end) {
+    if (rt < rt_end) {
       __builtin_amdgcn_s_waitcnt(0);
       lds_barrier();
-      tile_sync<T, TR, NW>(a, b0, rt, (int)(row_end - rt));
+      tile_sync<T, TR, NW>(a, b0, rt, (int)(rt_end - rt));
       lds_barrier();
-      process(a, S, b0, scr, rt, (int)(row_end - rt));
+      process(a, S, b0, scr, rt, (int)(rt_end - rt));
     }
 
     if (GRAM) {
@@ -813,14 +837,21 @@ hipError_t launch_pass16_t(const PassArgs<T>& pa, int64_t m,
   const Shape sh = shapes[pick];
   const int maxp = shape_maxp(sh, npairs);
   ArgsT<T> a{};
-  // rows split over 256 * per_cu workgroups (256 CUs on MI355X), at most
-  // tune.max_wg of them
+  // G = 256 * per_cu workgroups (256 CUs on MI355X), at most tune.max_wg,
+  // each with about m / G rows.  The tiles are dealt round-robin to the
+  // workgroups (measured on the tall P-1S, P-2S and BCGSI+ runs: 0.1-2 %
+  // faster than contiguous row ranges); BCGS_PASS16_INTERLEAVE=0 selects
+  // the contiguous ranges.
   const int64_t rpw =
       std::max(round_up64(cdiv(m, 256 * sh.per_cu), 64),
                round_up64(cdiv(m, std::max(1, tune.max_wg)), 64));
   const int G = (int)cdiv(m, rpw);
   a.m = pa.m; a.s = s; a.ncols = pa.ncols; a.ncols_p = pa.ncols_p;
   a.rows_per_wg = rpw;
+  {
+    const char* e = getenv("BCGS_PASS16_INTERLEAVE");
+    a.interleave = e ? atoi(e) != 0 : 1;
+  }
   a.q = pa.q; a.ldq = pa.ldq; a.nq = pa.nq;
   a.f = pa.f; a.ldf = pa.ldf; a.fcols = pa.fcols;
   a.e = pa.e; a.lde = pa.lde; a.ecols = pa.ecols;

@@ -4,10 +4,17 @@ profiles/.
     python -m paper_2507_21791_amd.prof_summary trace  <dir> <prefix> "<cmd>"
     python -m paper_2507_21791_amd.prof_summary counters <fetch_dir>
            <write_dir> <prefix> "<cmd>"
+    python -m paper_2507_21791_amd.prof_summary requests <read_dir>
+           <write_dir> "<cmd>"
 
 `trace` reads <dir>/<prefix>_kernel_trace.csv (a --kernel-trace run) and
 prints per-kernel launch counts and durations for this library's kernels
 (the input generation by torch/rocBLAS/rocSOLVER is summed on one line).
+
+`requests` reads two runs of the TCC_EA0 request-size counters (reads of
+32, 64 and 128 bytes; writes of 64 bytes or else 32) and prints the bytes
+they imply per launch, with no calibration: a check of the scale factors
+that `counters` derives.
 
 `counters` reads the FETCH_SIZE and WRITE_SIZE runs (one counter per run)
 and prints the per-launch HBM traffic of every library kernel, scaled by
@@ -100,7 +107,12 @@ def counters(dfetch, dwrite, prefix, cmd, root):
     wr = _counter(dwrite, "WRITE_SIZE")
     cal = {}
     for tag, rows in (("FETCH_SIZE", fe), ("WRITE_SIZE", wr)):
-        vals = [v for n, g, v in rows if "copyBuffer" in n and g == 131072]
+        # the calibration copies run before the first library kernel (the
+        # bench's own copy-rate measurement, 2 GiB copies, comes after it)
+        first = next((i for i, (n, g, v) in enumerate(rows) if ours(n)),
+                     len(rows))
+        vals = [v for n, g, v in rows[:first]
+                if "copyBuffer" in n and g == 131072]
         vals = [v for v in vals if v > 0.25 * GIB_KIB]
         vals = vals[-3:]
         cal[tag] = GIB_KIB / (sum(vals) / len(vals)) if vals else float("nan")
@@ -141,12 +153,70 @@ def counters(dfetch, dwrite, prefix, cmd, root):
     return "\n".join(out)
 
 
+RD_COUNTERS = ("TCC_EA0_RDREQ_32B_sum", "TCC_EA0_RDREQ_64B_sum",
+               "TCC_EA0_RDREQ_128B_sum", "TCC_EA0_RDREQ_sum")
+WR_COUNTERS = ("TCC_EA0_WRREQ_64B_sum", "TCC_EA0_WRREQ_sum")
+
+
+def _dispatches(d, names):
+    """{dispatch id: (kernel, grid, {counter: value})} in dispatch order."""
+    f = [x for x in os.listdir(d) if x.endswith("counter_collection.csv")][0]
+    out = OrderedDict()
+    for r in csv.DictReader(open(os.path.join(d, f))):
+        if r["Counter_Name"] not in names:
+            continue
+        k = out.setdefault(int(r["Dispatch_Id"]),
+                           (r["Kernel_Name"], int(r["Grid_Size"]), {}))
+        k[2][r["Counter_Name"]] = float(r["Counter_Value"])
+    return out
+
+
+def requests(drd, dwrite, cmd):
+    """HBM bytes from the L2-to-memory request counts by size (no
+    calibration): reads 32, 64 or 128 bytes, writes 64 bytes or else 32."""
+    rd = _dispatches(drd, RD_COUNTERS)
+    wr = _dispatches(dwrite, WR_COUNTERS)
+    per = defaultdict(lambda: [0, 0.0, 0.0, 0.0])
+    copies = []
+    for (i, (n, g, c)), (j, (n2, g2, w)) in zip(rd.items(), wr.items()):
+        rb = (32 * c["TCC_EA0_RDREQ_32B_sum"] + 64 * c["TCC_EA0_RDREQ_64B_sum"]
+              + 128 * c["TCC_EA0_RDREQ_128B_sum"])
+        w64 = w["TCC_EA0_WRREQ_64B_sum"]
+        wb = 64 * w64 + 32 * (w["TCC_EA0_WRREQ_sum"] - w64)
+        if ours(n):
+            a = per[short_name(n)]
+            a[0] += 1
+            a[1] += rb
+            a[2] += wb
+            a[3] += c["TCC_EA0_RDREQ_128B_sum"] / max(1.0, c["TCC_EA0_RDREQ_sum"])
+        elif "copyBuffer" in n and g == 131072 and not per:
+            copies.append((rb, wb))
+    out = ["# rocprofv3 HBM request summary (TCC_EA0 read / write request "
+           "counts by size, two runs)",
+           f"# command (twice, --pmc {' '.join(RD_COUNTERS)} / --pmc "
+           f"{' '.join(WR_COUNTERS)}): {cmd}"]
+    for rb, wb in copies[-3:]:
+        out.append(f"# plain 1 GiB device copy: read {rb / 2**30:.4f} GiB, "
+                   f"written {wb / 2**30:.4f} GiB")
+    out += ["# per-launch averages in GB (1e9 bytes); rd128 = share of read "
+            "requests that are 128 bytes",
+            f"{'kernel':52s} {'calls':>6s} {'read_GB':>9s} {'write_GB':>9s}"
+            f" {'total_GB':>9s} {'rd128':>6s}"]
+    for k, (n, rb, wb, f128) in sorted(per.items(),
+                                       key=lambda kv: -(kv[1][1] + kv[1][2])):
+        out.append(f"{k:52s} {n:6d} {rb / n / 1e9:9.4f} {wb / n / 1e9:9.4f}"
+                   f" {(rb + wb) / n / 1e9:9.4f} {f128 / n:6.3f}")
+    return "\n".join(out)
+
+
 def main(argv):
     root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
     if argv[1] == "trace":
         print(trace(argv[2], argv[3], argv[4]))
     elif argv[1] == "counters":
         print(counters(argv[2], argv[3], argv[4], argv[5], root))
+    elif argv[1] == "requests":
+        print(requests(argv[2], argv[3], argv[4]))
     else:
         raise SystemExit(__doc__)
 

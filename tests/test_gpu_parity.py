@@ -183,6 +183,26 @@ def test_fast_pass_takes_odd_rows_and_wide_blocks(m, n):
     compare(X, 16, "p-1s", host(Q), host(R), ws.info(), kappa=1e3)
 
 
+@pytest.mark.parametrize("interleave", ["0", "1"])
+@pytest.mark.parametrize("m,n,variant", [(40010, 128, "p-1s"),
+                                         (500, 64, "bcgsi+"),
+                                         (3001, 48, "p-2s")])
+def test_pass_tile_orders(monkeypatch, interleave, m, n, variant):
+    """Both assignments of row tiles to workgroups of the s <= 16 pass
+    (contiguous ranges, round-robin tiles), on ragged row counts, one with
+    fewer full tiles than workgroups (m = 500: the short tile alone on a
+    workgroup), meet the oracle's tolerances."""
+    import torch
+    from paper_2507_21791_amd import bcgs
+    monkeypatch.setenv("BCGS_PASS16_INTERLEAVE", interleave)
+    log(f"[gpu] tile order interleave={interleave} m={m} n={n} {variant}")
+    X = W.conditioned_host(m, n, 3, seed=7 * m + n)
+    Xd = to_device(X, torch.float64)
+    Q, R, ws = bcgs.qr(Xd, 16, variant)
+    torch.cuda.synchronize()
+    compare(X, 16, variant, host(Q), host(R), ws.info(), kappa=1e3)
+
+
 @pytest.mark.parametrize("variant", ["p-1s", "bcgsi+"])
 def test_full_size_tall_properties_and_sampled_block(variant):
     """The timed configuration itself (m = 2^22, n = 256, s = 16, launched
