@@ -575,8 +575,11 @@ def main():
         out["batched"] = bench_batched(args.batched_count, 3)
     if not args.no_served:
         pool, pool32 = served_pool(args.served_pool)
+        # 2000/s: far above capacity, so throughput is the capacity and the
+        # latencies include the backlog; 150/s: about half of capacity, the
+        # latency under a load the queue sustains (the headline p99)
         served = [bench_served(args.served_n, 2000.0, "fp64", pool, pool32),
-                  bench_served(max(1, args.served_n // 3), 300.0, "fp64",
+                  bench_served(max(1, args.served_n // 2), 150.0, "fp64",
                                pool, pool32),
                   bench_served(args.served_n, 2000.0, "fp32-bulk", pool,
                                pool32)]
@@ -586,7 +589,9 @@ def main():
                          "log-uniform 4096..2^21, n 16..512, kappa "
                          "1e2..1e8) drawn with replacement"),
             "runs": served}
-        out["p99_latency_ms"] = served[0]["p99_ms"]
+        out["p99_latency_ms"] = served[1]["p99_ms"]
+        out["p99_latency_load"] = ("fp64 requests at 150/s (about half of "
+                                   "the measured capacity)")
         del pool, pool32
         torch.cuda.empty_cache()
     if not args.no_cpu:
