@@ -144,13 +144,16 @@ def kernel_name(kind, tag):
                (16, 4): 272, (16, 8): 544}.get((tr, nw), 0)
         if (tr, nw, nbuf) == (16, 4, 4):
             cap = 272
+        if pc == 2 and scr2:
+            cap = 256
         if f32:
             cap = {(32, 8): 544}.get((tr, nw), 272)
         gram = "true" if ntb else "false"
         r = "true" if reg else "false"
         t = "float" if f32 else "double"
         if pc == 2:
-            return (f"pass16_kernel<{t}, {tr}, {nbuf}, {cap}, {maxp}, "
+            k = "pass16_s2_kernel" if scr2 else "pass16_kernel"
+            return (f"{k}<{t}, {tr}, {nbuf}, {cap}, {maxp}, "
                     f"{gram}, {max(ntb, 1)}, {r}>")
         return (f"pass16_deep_kernel<{t}, {tr}, {nbuf}, {cap}, {nw}, "
                 f"{'true' if scr2 else 'false'}, {maxp}, {gram}, "

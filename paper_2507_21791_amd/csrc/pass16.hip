@@ -3,11 +3,11 @@
 // updates of Alg. 1 / Alg. 2 fused with the tall-skinny Gram products of one
 // synchronization point), organised for gfx950:
 //
-//  * 4 waves per workgroup.  Either two workgroups per CU with two LDS tile
-//    buffers each, or one workgroup per CU with three or four buffers (a
-//    deeper copy pipeline for the widest passes).  The row range of a
-//    workgroup is walked in full tiles of TR rows (16, 32 or 64); a short
-//    last tile is staged synchronously after the loop.
+//  * Either two 4-wave workgroups per CU with two LDS tile buffers each, or
+//    one workgroup per CU with 8 waves or with four buffers.  Full tiles of
+//    TR rows (16, 32 or 64) are dealt round-robin to the workgroups, so the
+//    workgroups running together read one narrow band of rows of every
+//    column; the short last tile is staged synchronously after the loop.
 //  * Tiles arrive by direct-to-LDS copies (global_load_lds_dwordx4) issued
 //    NBUF - 1 tiles ahead.  Waiting for a tile counts only the copies issued
 //    after it (vector memory operations complete in issue order), so the
@@ -28,8 +28,10 @@
 //    of the coefficient fragments in registers for the whole kernel.  When
 //    a pass has two updates, both read the staged (old) columns (the second
 //    one's coefficients have the first one's folded in by the epilogue), so
-//    they share the fragment loads and their K-range partial sums are
-//    combined in one LDS round; the combine writes the results both to HBM
+//    they share the fragment loads.  Their K-range partial sums are combined
+//    through LDS, one round per update, or one round for both where the
+//    shape has room for both partial-sum areas (three barriers per tile
+//    instead of five); the combine writes the results both to HBM
 //    (coalesced) and into the tile for the Gram.
 //  * Gram A^T B: the (A block, B block) pairs of 16x16 outputs are dealt
 //    round-robin to the waves (equal MFMA counts), which accumulate them in

@@ -152,7 +152,20 @@ __device__ void tile_sync(const ArgsT<T>& a, T* buf, int64_t r0, int rows) {
   }
 }
 
-// Sum the K-range partial products of one block update (scr: [KG][TR][17])
+// Partial-sum area of a block update: [KG][TR] rows of 16 columns.  Binary64
+// rows hold 16 values with column c of row r at position c ^ (r mod 16);
+// binary32 rows are padded to 17.  Either way the MFMA result writes (16
+// columns of 4 rows per instruction) and the combine reads (16 or 32 rows of
+// one column per half wave) hit distinct banks.
+template <typename T>
+constexpr int kScrRow = sizeof(T) == 8 ? 16 : 17;
+template <typename T>
+__device__ __forceinline__ int sidx(int row, int col) {
+  if constexpr (sizeof(T) == 8) return row * 16 + (col ^ (row & 15));
+  return row * 17 + col;
+}
+
+// Sum the K-range partial products of one block update (scr: [KG][TR] rows)
 // into the tile columns [uc0, uc0 + s) and into dst (rows < rows).
 template <typename T, int TR, int KG, int NW>
 __device__ __forceinline__ void combine(const ArgsT<T>& a, T* tile,
@@ -163,7 +176,7 @@ __device__ __forceinline__ void combine(const ArgsT<T>& a, T* tile,
     if (c >= a.s) continue;
     T part[KG];
 #pragma unroll
-    for (int k = 0; k < KG; ++k) part[k] = scr[(k * TR + r) * 17 + c];
+    for (int k = 0; k < KG; ++k) part[k] = scr[sidx<T>(k * TR + r, c)];
     T sum = 0;
 #pragma unroll
     for (int k = 0; k < KG; ++k) sum += part[k];
@@ -172,7 +185,8 @@ __device__ __forceinline__ void combine(const ArgsT<T>& a, T* tile,
   }
 }
 
-// One workgroup per row range.  TR tile rows; NBUF tile buffers of CAP
+// A workgroup streams its share of the row tiles (round-robin tiles, or a
+// contiguous row range).  TR tile rows; NBUF tile buffers of CAP
 // columns, each its own LDS object; PC workgroups per CU; NW waves; SCR2:
 // LDS room for both updates' partial sums; MAXP Gram pairs per wave; NTB
 // B blocks; REG: tiles staged through registers instead of direct copies.
@@ -329,20 +343,20 @@ struct Kernel {
     }
     acc1 += acc1b;
     acc2 += acc2b;
-    // partial sums: scr[kg][row][col], row stride 17; result v at lane l is
-    // row mb*16 + drow(lk, v), column li
+    // partial sums: scr[kg][row][col] (sidx); result v at lane l is row
+    // mb*16 + drow(lk, v), column li
     T* scr1 = scr;
-    T* scr2 = SCR2 ? scr + KG * TR * 17 : scr;
-    const int wbase = (S.kg * TR + S.mb * 16) * 17 + li;
+    T* scr2 = SCR2 ? scr + KG * TR * kScrRow<T> : scr;
+    const int wrow = S.kg * TR + S.mb * 16;
     if (U1) {
 #pragma unroll
       for (int v = 0; v < 4; ++v)
-        scr1[wbase + Elt<T>::drow(lk, v) * 17] = acc1[v];
+        scr1[sidx<T>(wrow + Elt<T>::drow(lk, v), li)] = acc1[v];
     }
     if (U2 && (SCR2 || !U1)) {
 #pragma unroll
       for (int v = 0; v < 4; ++v)
-        scr2[wbase + Elt<T>::drow(lk, v) * 17] = acc2[v];
+        scr2[sidx<T>(wrow + Elt<T>::drow(lk, v), li)] = acc2[v];
     }
     lds_barrier();
     if (U1)
@@ -356,7 +370,7 @@ struct Kernel {
       // one partial-sum area: the second update's round
 #pragma unroll
       for (int v = 0; v < 4; ++v)
-        scr[wbase + Elt<T>::drow(lk, v) * 17] = acc2[v];
+        scr[sidx<T>(wrow + Elt<T>::drow(lk, v), li)] = acc2[v];
       lds_barrier();
       combine<T, TR, KG, NW>(a, tile, scr, a.u2_c0, a.dst2, a.ldd2, r0,
                              rows);
@@ -469,9 +483,18 @@ struct Kernel {
   static __device__ __forceinline__ void run(const Args& a) {
     __shared__ T b0[TE];
     __shared__ T b1[TE];
-    __shared__ T b2[NBUF > 2 ? TE : 1];
-    __shared__ T b3[NBUF > 3 ? TE : 1];
-    __shared__ T scr[(SCR2 ? 2 : 1) * KG * TR * 17];
+    // the third and fourth buffers exist (take LDS) only with NBUF > 2, 3
+    T* b2 = nullptr;
+    T* b3 = nullptr;
+    if constexpr (NBUF > 2) {
+      __shared__ T b2s[TE];
+      b2 = b2s;
+    }
+    if constexpr (NBUF > 3) {
+      __shared__ T b3s[TE];
+      b3 = b3s;
+    }
+    __shared__ T scr[(SCR2 ? 2 : 1) * KG * TR * kScrRow<T>];
     T* const bufs[4] = {b0, b1, b2, b3};
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform
@@ -543,8 +566,8 @@ struct Kernel {
     for (int idx = a.ncols_p * TR + tid; idx < TE; idx += NW * 64) {
       b0[idx] = 0;
       b1[idx] = 0;
-      if (NBUF > 2) b2[idx] = 0;
-      if (NBUF > 3) b3[idx] = 0;
+      if constexpr (NBUF > 2) b2[idx] = 0;
+      if constexpr (NBUF > 3) b3[idx] = 0;
     }
 
     // ---- full tiles ----
@@ -632,6 +655,15 @@ void pass16_kernel(ArgsT<T> a) {
   Kernel<T, TR, NBUF, CAP, 2, 4, false, MAXP, GRAM, NTB, REG>::run(a);
 }
 
+// the same with both partial-sum areas (one combine round fewer per tile
+// when a pass has both block updates)
+template <typename T, int TR, int NBUF, int CAP, int MAXP, bool GRAM, int NTB,
+          bool REG>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
+void pass16_s2_kernel(ArgsT<T> a) {
+  Kernel<T, TR, NBUF, CAP, 2, 4, true, MAXP, GRAM, NTB, REG>::run(a);
+}
+
 // one workgroup of NW waves per CU
 template <typename T, int TR, int NBUF, int CAP, int NW, bool SCR2, int MAXP,
           bool GRAM, int NTB, bool REG>
@@ -650,7 +682,11 @@ static hipError_t go(const ArgsT<T>& a, int G, hipStream_t st, int* tag) {
          (PC + (sizeof(T) == 4 ? 4 : 0)) * 10000000 +
          (NBUF + (REG ? 5 : 0)) * 1000000 + (SCR2 ? 100000 : 0) +
          (TR % 100) * 1000 + MAXP * 10 + (GRAM ? NTB : 0);
-  if constexpr (PC == 2)
+  if constexpr (PC == 2 && SCR2)
+    hipLaunchKernelGGL(
+        (pass16_s2_kernel<T, TR, NBUF, CAP, MAXP, GRAM, NTB, REG>),
+        dim3((unsigned)G), dim3(256), 0, st, a);
+  else if constexpr (PC == 2)
     hipLaunchKernelGGL(
         (pass16_kernel<T, TR, NBUF, CAP, MAXP, GRAM, NTB, REG>),
         dim3((unsigned)G), dim3(256), 0, st, a);
@@ -670,13 +706,15 @@ struct Shape { int tr, nbuf, cap, per_cu, nw, scr2; };
 // entry.  Taller tiles stream faster (each copy instruction covers fewer
 // columns, so fewer pages and longer runs per column: on MI355X about 4.2,
 // 5.7 and 6.3 TB/s for 16, 32 and 64 rows), so wide passes take one
-// workgroup of 8 waves per CU with 32- or 64-row tiles.  The last shape
-// takes up to 544 columns (n up to 512 at s = 16) in one 8-wave workgroup
-// per CU.
+// workgroup of 8 waves per CU with 32- or 64-row tiles.  Shape 6 takes up
+// to 544 columns (n up to 512 at s = 16) in one 8-wave workgroup per CU.
+// Shape 7 is shape 4 with room for both updates' partial sums (one combine
+// round per tile instead of two) at 256 columns, the most that keeps two
+// workgroups per CU (2 x 81920 bytes of LDS).
 constexpr Shape kShapes[] = {
     {64, 2, 64, 2, 4, 0},  {64, 2, 128, 1, 8, 0}, {32, 2, 272, 1, 8, 0},
     {32, 2, 128, 2, 4, 0}, {16, 2, 272, 2, 4, 0}, {16, 4, 272, 1, 4, 1},
-    {16, 2, 544, 1, 8, 0}};
+    {16, 2, 544, 1, 8, 0}, {16, 2, 256, 2, 4, 1}};
 constexpr int kNShapes = sizeof(kShapes) / sizeof(kShapes[0]);
 
 // Binary32 shapes: the same bytes per column and tile as the 16-row
@@ -759,6 +797,7 @@ hipError_t dispatch(int pick, const ArgsT<T>& a, int G, bool gram, int ntb,
         if constexpr (!REG) return GS(16, 4, 272, 1, 4, true);
         return hipErrorNotSupported;
       case 6: return GS(16, 2, 544, 1, 8, false);
+      case 7: return GS(16, 2, 256, 2, 4, true);
     }
   } else {
     switch (pick) {
@@ -822,10 +861,18 @@ hipError_t launch_pass16_t(const PassArgs<T>& pa, int64_t m,
     // Gram (P-1S, P-2S) are bound by the MFMA work and run best with
     // 16-row tiles, two workgroups per CU; the other wide passes are bound
     // by the stream and take the 32-row, 8-wave shape.
-    static const int kHeavy[] = {0, 3, 4, 2, 5, 1, 6};
-    static const int kLight[] = {0, 3, 2, 4, 5, 1, 6};
+    static const int kHeavy[] = {0, 3, 7, 4, 2, 5, 1, 6};
+    static const int kLight[] = {0, 3, 2, 4, 7, 5, 1, 6};
     static_assert(sizeof(kHeavy) / sizeof(int) == nshapes, "every shape");
     const int* order = (pa.gram && ntb == 2) ? kHeavy : kLight;
+    // Measured per pass (tall PIPI+, P-1S): a pass with one Gram B block and
+    // a block update runs faster in shape 7 than in the 8-wave 32-row shape
+    // from 129 up to 208 columns (256 with both updates); wider, or with the
+    // Gram or an update alone (BCGSI+), the 32-row shape is faster.
+    if (pick < 0 && pa.gram && ntb == 1 && (pa.upd1 || pa.upd2) &&
+        pa.ncols_p > 128 && pa.ncols_p <= (pa.upd1 && pa.upd2 ? 256 : 208) &&
+        shape_fits<T>(shapes[7], pa.ncols_p, shared, npairs, reg))
+      pick = 7;
     for (int i = 0; pick < 0 && i < nshapes; ++i)
       if (shape_fits<T>(shapes[order[i]], pa.ncols_p, shared, npairs, reg))
         pick = order[i];
