@@ -77,7 +77,10 @@ __device__ __forceinline__ int update_ksplit(int tr, int sp) {
   return nt >= kWaves ? 1 : kWaves / nt;
 }
 
-template <typename T>
+// MULTI: K-steps four at a time on four accumulators (for the kernels
+// without Gram accumulators, whose registers allow it); otherwise one
+// accumulator, so the Gram kernels keep their occupancy.
+template <typename T, bool MULTI>
 __device__ void update_partials(const PassArgs<T>& a, const T* tile,
                                 int trp, T* scr, int uc0,
                                 const double* __restrict__ F) {
@@ -95,14 +98,39 @@ __device__ void update_partials(const PassArgs<T>& a, const T* tile,
     const int rb = t % mb, cb = t / mb;
     typename Mma<T>::acc acc = {0, 0, 0, 0};
     const int kb = ks * kper, ke = min(ksteps, kb + kper);
-    for (int kk = kb; kk < ke; ++kk) {
+    auto operands = [&](int kk, T& av, T& bv) {
       const int k = kk * 4 + lk;
-      T av = 0, bv = 0;
-      if (k < K) {
+      av = 0;
+      bv = 0;
+      if (kk < ke && k < K) {
         av = tile[k * trp + rb * 16 + li];
         bv = static_cast<T>(F[k * sp + cb * 16 + li]);
       }
-      acc = Mma<T>::mac(av, bv, acc);
+    };
+    if constexpr (MULTI) {
+      // four independent MFMA chains, the operand loads of a group issued
+      // together, summed in a fixed order at the end
+      typename Mma<T>::acc acc1 = acc, acc2 = acc, acc3 = acc;
+      for (int kk = kb; kk < ke; kk += 4) {
+        T a0, b0, a1, b1, a2, b2, a3, b3;
+        operands(kk, a0, b0);
+        operands(kk + 1, a1, b1);
+        operands(kk + 2, a2, b2);
+        operands(kk + 3, a3, b3);
+        acc = Mma<T>::mac(a0, b0, acc);
+        acc1 = Mma<T>::mac(a1, b1, acc1);
+        acc2 = Mma<T>::mac(a2, b2, acc2);
+        acc3 = Mma<T>::mac(a3, b3, acc3);
+      }
+      acc += acc1;
+      acc2 += acc3;
+      acc += acc2;
+    } else {
+      for (int kk = kb; kk < ke; ++kk) {
+        T av, bv;
+        operands(kk, av, bv);
+        acc = Mma<T>::mac(av, bv, acc);
+      }
     }
     T* out = scr + (size_t)ks * tr * srow;
 #pragma unroll
@@ -175,8 +203,9 @@ __global__ __launch_bounds__(kThreads) void pass_kernel(PassArgs<T> a) {
       T* scr2 = a.upd1 ? scr + (size_t)update_ksplit(tr, a.sp) * tr *
                                         (a.sp + 1)
                             : scr;
-      if (a.upd1) update_partials(a, tile, trp, scr, a.u1_c0, a.c1);
-      if (a.upd2) update_partials(a, tile, trp, scr2, a.u2_c0, a.c2);
+      if (a.upd1) update_partials<T, !GRAM>(a, tile, trp, scr, a.u1_c0, a.c1);
+      if (a.upd2)
+        update_partials<T, !GRAM>(a, tile, trp, scr2, a.u2_c0, a.c2);
       __syncthreads();
       if (a.upd1)
         update_finish(a, tile, trp, scr, a.u1_c0, a.dst1, a.ldd1, r0, rows);
