@@ -183,6 +183,29 @@ def test_fast_pass_takes_odd_rows_and_wide_blocks(m, n):
     compare(X, 16, "p-1s", host(Q), host(R), ws.info(), kappa=1e3)
 
 
+@pytest.mark.parametrize("variant", ["p-1s", "pipi+", "bcgsi+"])
+def test_two_area_shape_register_staged(variant):
+    """n = 256 at an odd leading dimension: the passes of 144 to 256
+    columns run the two-partial-sum shape (P-1S) or the 16-row shape for
+    one Gram B block with an update (PIPI+) in register-staged form;
+    BCGSI+ keeps the 32-row shape.  Results meet the oracle's tolerances."""
+    import torch
+    from paper_2507_21791_amd import bcgs
+    m, n = 20001, 256
+    log(f"[gpu] two-area shape, register staged m={m} n={n} {variant}")
+    X = W.conditioned_host(m, n, 3, seed=m + 3)
+    Xd = to_device(X, torch.float64)
+    stream = torch.cuda.current_stream()
+    bcgs.profile_start(stream)
+    Q, R, ws = bcgs.qr(Xd, 16, variant)
+    recs = bcgs.profile_stop(stream)
+    tags = [r["tag"] for r in recs if r["kind"] == "pass"]
+    assert tags and all((t // 10 ** 6) % 10 >= 5 for t in tags), tags
+    if variant == "p-1s":
+        assert any((t // 10 ** 5) % 10 == 1 for t in tags), tags
+    compare(X, 16, variant, host(Q), host(R), ws.info(), kappa=1e3)
+
+
 @pytest.mark.parametrize("interleave", ["0", "1"])
 @pytest.mark.parametrize("m,n,variant", [(40010, 128, "p-1s"),
                                          (500, 64, "bcgsi+"),
