@@ -755,7 +755,7 @@ hipError_t launch_epilogue(const EpiArgs& a, hipStream_t st) {
   switch (a.s) {
 #define EPI(S_) case S_: hipLaunchKernelGGL(epilogue_kernel<S_>, dim3(1), \
                                             dim3(kThreads), 0, st, a); break;
-    EPI(4) EPI(8) EPI(16)
+    EPI(4) EPI(8) EPI(16) EPI(32)
 #undef EPI
     default:
       hipLaunchKernelGGL(epilogue_kernel<0>, dim3(1), dim3(kThreads), 0, st,
