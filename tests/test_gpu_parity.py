@@ -208,6 +208,7 @@ def test_two_area_shape_register_staged(variant):
 
 @pytest.mark.parametrize("interleave", ["0", "1"])
 @pytest.mark.parametrize("m,n,variant", [(40010, 128, "p-1s"),
+                                         (20010, 256, "p-1s"),
                                          (500, 64, "bcgsi+"),
                                          (3001, 48, "p-2s")])
 def test_pass_tile_orders(monkeypatch, interleave, m, n, variant):
