@@ -432,19 +432,28 @@ struct Kernel {
         for (int q = 0; q < 4; ++q)
           bq[q] = *reinterpret_cast<const double2*>(
               tile + at<T, TR>(bcol + q, r));
+        // With two B blocks (pairs spread evenly: the waves differ by at
+        // most one) and up to 7 pair slots the loop is branch-free: a slot
+        // past this wave's pairs works on a valid column (pair npairs - 1)
+        // and its sums are never stored, so the compiler batches all
+        // operand loads (the launcher picks MAXP = the most pairs any wave
+        // has).  Otherwise idle slots are skipped by branches: with more
+        // slots the operands would not fit the registers, and with one B
+        // block many waves would idle a slot.
+        constexpr bool kBranchFree = NTB == 2 && MAXP <= 7;
 #pragma unroll
         for (int i = 0; i < MAXP; ++i) {
-          const int p = wave + NW * i;
-          if (p < S.npairs) {          // wave-uniform
-            const double2 af = *reinterpret_cast<const double2*>(
-                tile + at<T, TR>((p / NTB) * 16 + li, r));
+          const int p0 = wave + NW * i;
+          if (!kBranchFree && p0 >= S.npairs) continue;   // wave-uniform
+          const int p = min(p0, S.npairs - 1);
+          const double2 af = *reinterpret_cast<const double2*>(
+              tile + at<T, TR>((p / NTB) * 16 + li, r));
 #pragma unroll
-            for (int q = 0; q < 4; ++q)
-              S.acc[i][q] = mfma4(af.x, bq[q].x, (double)S.acc[i][q]);
+          for (int q = 0; q < 4; ++q)
+            S.acc[i][q] = mfma4(af.x, bq[q].x, (double)S.acc[i][q]);
 #pragma unroll
-            for (int q = 0; q < 4; ++q)
-              S.acc[i][q] = mfma4(af.y, bq[q].y, (double)S.acc[i][q]);
-          }
+          for (int q = 0; q < 4; ++q)
+            S.acc[i][q] = mfma4(af.y, bq[q].y, (double)S.acc[i][q]);
         }
         asm volatile("" ::: "memory");
       }
@@ -747,36 +756,38 @@ static bool shape_fits(const Shape& sh, int ncols_p, int shared_ksteps,
   return ncols_p <= sh.cap;
 }
 
+// Gram launch with the smallest instantiated pair count per wave M >= maxp:
+// every count from 2 up to the most pairs a wave of this shape can get (NTB
+// B blocks), at most 9.
+template <typename T, int TR, int NBUF, int CAP, int PC, int NW, bool SCR2,
+          bool REG, int NTB, int M>
+static hipError_t go_maxp(const ArgsT<T>& a, int G, int maxp, hipStream_t st,
+                          int* tag) {
+  constexpr int kTop = ((CAP / 16) * NTB + NW - 1) / NW;
+  if constexpr (M >= kTop || M >= 9) {
+    return go<T, TR, NBUF, CAP, PC, NW, SCR2, M, true, NTB, REG>(a, G, st,
+                                                                 tag);
+  } else {
+    if (maxp <= M)
+      return go<T, TR, NBUF, CAP, PC, NW, SCR2, M, true, NTB, REG>(a, G, st,
+                                                                   tag);
+    return go_maxp<T, TR, NBUF, CAP, PC, NW, SCR2, REG, NTB, M + 1>(
+        a, G, maxp, st, tag);
+  }
+}
+
 template <typename T, int TR, int NBUF, int CAP, int PC, int NW, bool SCR2,
           bool REG>
 static hipError_t go_shape(const ArgsT<T>& a, int G, bool gram, int ntb,
                            int maxp, hipStream_t st, int* tag) {
-#define GO(M_, G_, N_) \
-  go<T, TR, NBUF, CAP, PC, NW, SCR2, M_, G_, N_, REG>(a, G, st, tag)
-  // largest pair count per wave this capacity can produce (two B blocks)
-  constexpr int kTop = ((CAP / 16) * 2 + NW - 1) / NW;
-  if (!gram) return GO(1, false, 1);
-  if (ntb == 1) {
-    if (kTop <= 2 || maxp <= 2) return GO(2, true, 1);
-    if constexpr (kTop > 2) {
-      if (kTop <= 5 || maxp <= 5) return GO(5, true, 1);
-      if constexpr (kTop > 5) {
-        if (kTop <= 7 || maxp <= 7) return GO(7, true, 1);
-        if constexpr (kTop > 7) return GO(9, true, 1);
-      }
-    }
-  } else {
-    if (kTop <= 2 || maxp <= 2) return GO(2, true, 2);
-    if constexpr (kTop > 2) {
-      if (kTop <= 5 || maxp <= 5) return GO(5, true, 2);
-      if constexpr (kTop > 5) {
-        if (kTop <= 7 || maxp <= 7) return GO(7, true, 2);
-        if constexpr (kTop > 7) return GO(9, true, 2);
-      }
-    }
-  }
-  return hipErrorNotSupported;
-#undef GO
+  if (!gram)
+    return go<T, TR, NBUF, CAP, PC, NW, SCR2, 1, false, 1, REG>(a, G, st,
+                                                                tag);
+  if (ntb == 1)
+    return go_maxp<T, TR, NBUF, CAP, PC, NW, SCR2, REG, 1, 2>(a, G, maxp, st,
+                                                              tag);
+  return go_maxp<T, TR, NBUF, CAP, PC, NW, SCR2, REG, 2, 2>(a, G, maxp, st,
+                                                            tag);
 }
 
 // Launch shape `pick` of the storage type's list (REG: register-staged
