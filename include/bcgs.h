@@ -83,7 +83,10 @@ typedef enum {
  *   pivot   0-based pivot index inside that s x s factorization
  *   stage   0: the first intra-orthogonalization (S_{k,k}),
  *           1: the second one (Y_{k,k}), of Alg. 2
- *   syncs   number of device-wide reductions the factorization performed
+ *   syncs   synchronization points (section 1) the factorization ran,
+ *           counted on the device: each fixed-order reduction of the
+ *           per-workgroup Gram partials and each TSQR tree root adds one
+ *           as it completes (a breakdown does not stop the count)
  *   value   the offending pivot value */
 typedef struct {
     int32_t status;
@@ -130,8 +133,8 @@ size_t bcgs_workspace_size(int64_t m, int64_t n, int64_t s,
                            bcgs_variant variant, bcgs_precision precision);
 
 /* Number of device-wide reductions ("synchronization points", section 1)
- * the factorization of an m x n matrix with block width s performs:
- * q + 1 for BCGSI+P-1S and BCGSI+1s, 2q for BCGSI+P-2S, 2q - 1 for
+ * the factorization of an m x n matrix with block width s is scheduled to
+ * perform (a completed run reports what ran in bcgs_info.syncs): q + 1 for BCGSI+P-1S and BCGSI+1s, 2q for BCGSI+P-2S, 2q - 1 for
  * BCGS-PIPI+, 4q - 3 for BCGSI+ (Table 1 gives the per-block-column rates
  * q, q, 2q, 2q, 4q).  -1 on invalid arguments. */
 int32_t bcgs_sync_count(int64_t m, int64_t n, int64_t s,

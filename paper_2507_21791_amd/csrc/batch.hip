@@ -412,7 +412,7 @@ bcgs_status bcgs_tuning_set(int64_t m, int64_t n, int64_t s,
                             bcgs_variant variant, bcgs_precision precision,
                             const bcgs_tuning* choice) {
   if (s < 1 || s > kMaxS || n < 1 || m < n) return BCGS_ERR_ARG;
-  if (variant < BCGS_I_PLUS || variant > BCGS_P_1S) return BCGS_ERR_ARG;
+  if (variant < BCGS_I_PLUS || variant > BCGS_I_PLUS_1S) return BCGS_ERR_ARG;
   if (precision != BCGS_FP64 && precision != BCGS_FP32_BULK)
     return BCGS_ERR_ARG;
   if (!choice) {

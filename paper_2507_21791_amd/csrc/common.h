@@ -143,8 +143,10 @@ bcgs_status run_problem(const Plan& p, const void* X, int64_t ldx, void* Q,
 // *tag receives the kernel instantiation (see bcgs_launch_record).
 template <typename T>
 hipError_t launch_pass(const PassArgs<T>& a, int G, hipStream_t st, int* tag);
+// syncs: device counter of completed synchronization points (the info
+// record's field), incremented once by each reduction; may be null
 hipError_t launch_gram_reduce(const double* partial, int G, int64_t elems,
-                              double* out, hipStream_t st);
+                              double* out, int32_t* syncs, hipStream_t st);
 // Fast path for s <= 16 (pass16.hip); hipErrorNotSupported when it does not
 // apply (nothing launched).
 hipError_t launch_pass16(const PassArgs<double>& a, int64_t m,
@@ -163,10 +165,12 @@ hipError_t launch_epilogue(const EpiArgs& a, hipStream_t st);
 // TSQR of the m x s block v (leading dimension ldv) into dst (may equal v);
 // the s x s factor R (positive diagonal) goes to r_out(i, j) =
 // r_out[i * r_rs + j * r_cs] (full square, zeros below the diagonal).
+// The root of the reduction tree increments *syncs once (may be null).
 template <typename T>
 hipError_t launch_tsqr(const TsqrPlan& tp, const T* v, int64_t ldv, T* dst,
                        int64_t ldd, int64_t m, double* ws, double* r_out,
-                       int64_t r_rs, int64_t r_cs, hipStream_t st);
+                       int64_t r_rs, int64_t r_cs, int32_t* syncs,
+                       hipStream_t st);
 
 hipError_t launch_fill(double* p, int64_t rows, int64_t cols, int64_t ld,
                        double value, hipStream_t st);

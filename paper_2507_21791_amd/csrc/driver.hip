@@ -93,13 +93,15 @@ static int planned_syncs(int variant, int q) {
 
 void prof_retag(int tag);
 
-__global__ void info_init_kernel(bcgs_info* info, int syncs) {
+// syncs starts at zero; every reduction and every TSQR root adds one as it
+// completes, so the record reports the synchronization points that ran
+__global__ void info_init_kernel(bcgs_info* info) {
   if (threadIdx.x == 0) {
     info->status = BCGS_OK;
     info->block = -1;
     info->pivot = -1;
     info->stage = -1;
-    info->syncs = syncs;
+    info->syncs = 0;
     info->reserved = 0;
     info->value = 0.0;
   }
@@ -219,7 +221,7 @@ struct Run {
     prof_retag(tag);
     if (d.gram)
       check(launch_gram_reduce(a.partial, G, (int64_t)a.ga_p * a.gbn_p,
-                               dws(p.off_gram), st));
+                               dws(p.off_gram), &info->syncs, st));
     gram_ld_last = a.ga_p;
   }
   int64_t gram_ld_last = 0;
@@ -249,7 +251,7 @@ struct Run {
   void tsqr(const T* v, int64_t ldv, T* dst, double* rout, int64_t rs,
             int64_t cs) {
     check(launch_tsqr(p.tsqr, v, ldv, dst, ldq, p.m, dws(p.off_tsqr), rout,
-                      rs, cs, st));
+                      rs, cs, &info->syncs, st));
   }
 
   void run() {
@@ -261,8 +263,7 @@ struct Run {
   void run_steps() {
     const int s = p.s, q = p.q, sp = p.sp;
     check(launch_fill(R, p.n, p.n, ldr, 0.0, st));
-    hipLaunchKernelGGL(info_init_kernel, dim3(1), dim3(64), 0, st, info,
-                       planned_syncs(p.variant, q));
+    hipLaunchKernelGGL(info_init_kernel, dim3(1), dim3(64), 0, st, info);
     check(hipGetLastError());
     // [Q_0, R_00] = TSQR(X_0)
     tsqr(xb(0), ldx, qb(0), R, 1, ldr);

@@ -266,7 +266,7 @@ constexpr int kRedWaves = 16;
 
 __global__ __launch_bounds__(kRedWaves * 64) void gram_reduce_kernel(
     const double* __restrict__ partial, int G, int64_t elems,
-    double* __restrict__ out) {
+    double* __restrict__ out, int32_t* syncs) {
   __shared__ double red[kRedWaves][64];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int64_t e = (int64_t)blockIdx.x * 64 + lane;
@@ -289,15 +289,18 @@ __global__ __launch_bounds__(kRedWaves * 64) void gram_reduce_kernel(
     for (int i = 1; i < kRedWaves; ++i) t += red[i][lane];
     out[e] = t;
   }
+  // one synchronization point completed (counted by one thread)
+  if (syncs != nullptr && blockIdx.x == 0 && tid == 0) *syncs += 1;
 }
 
 hipError_t launch_gram_reduce(const double* partial, int G, int64_t elems,
-                              double* out, hipStream_t st) {
+                              double* out, int32_t* syncs, hipStream_t st) {
   const int64_t blocks = cdiv(elems, 64);
   prof_begin(BCGS_KERNEL_REDUCE, 0, 8.0 * elems * (G + 1),
              (double)elems * G);
   hipLaunchKernelGGL(gram_reduce_kernel, dim3((unsigned)blocks),
-                     dim3(kRedWaves * 64), 0, st, partial, G, elems, out);
+                     dim3(kRedWaves * 64), 0, st, partial, G, elems, out,
+                     syncs);
   prof_end();
   return hipGetLastError();
 }

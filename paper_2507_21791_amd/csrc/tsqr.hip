@@ -247,7 +247,7 @@ template <int S>
 __global__ __launch_bounds__(kT) void node_kernel(
     const double* __restrict__ rprev, int64_t nprev, int fan, int s,
     double* __restrict__ rcur, double* __restrict__ qcur, int is_root,
-    double* r_out, int64_t r_rs, int64_t r_cs) {
+    double* r_out, int64_t r_rs, int64_t r_cs, int32_t* syncs) {
   extern __shared__ double lds[];
   const Geo<S> geo(s);
   const Smem sm = carve(lds, s);
@@ -275,6 +275,8 @@ __global__ __launch_bounds__(kT) void node_kernel(
       if (geo.row(k) == geo.c) sgn[geo.c] = a[k] < 0.0 ? -1.0 : 1.0;
   }
   __syncthreads();
+  // the root completes the synchronization point of this TSQR
+  if (is_root && syncs != nullptr && threadIdx.x == 0) *syncs += 1;
   if (!geo.active) return;
   double* rn = rcur + (size_t)node * s * s;
   double* qn = qcur + (size_t)node * rows * s;
@@ -355,7 +357,7 @@ template <typename T>
 hipError_t launch_wave_tsqr(const TsqrPlan& tp, const T* v, int64_t ldv,
                             T* dst, int64_t ldd, int64_t m, double* ws,
                             double* r_out, int64_t r_rs, int64_t r_cs,
-                            hipStream_t st);
+                            int32_t* syncs, hipStream_t st);
 
 // s <= 16: one wave per chunk (tsqr_wave.hip); wider blocks: one workgroup
 // per chunk (this file)
@@ -406,7 +408,7 @@ template <typename T, int S>
 static hipError_t launch_tsqr_s(const TsqrPlan& tp, const T* v, int64_t ldv,
                                 T* dst, int64_t ldd, int64_t m, double* ws,
                                 double* r_out, int64_t r_rs, int64_t r_cs,
-                                hipStream_t st) {
+                                int32_t* syncs, hipStream_t st) {
   const int s = tp.s, fan = tp.fan;
   const size_t lds = (size_t)tq::lds_doubles(s) * sizeof(double);
   const double ss = (double)s * s, esz = sizeof(T);
@@ -424,7 +426,7 @@ static hipError_t launch_tsqr_s(const TsqrPlan& tp, const T* v, int64_t ldv,
                        dim3(kThreads), lds, st, ws + tp.r_off[l - 1],
                        tp.nodes[l - 1], fan, s, ws + tp.r_off[l],
                        ws + tp.q_off[l], l == tp.levels ? 1 : 0, r_out, r_rs,
-                       r_cs);
+                       r_cs, syncs);
     prof_end();
   }
   tsqr_down(tp, ws, st);
@@ -439,28 +441,30 @@ static hipError_t launch_tsqr_s(const TsqrPlan& tp, const T* v, int64_t ldv,
 template <typename T>
 hipError_t launch_tsqr(const TsqrPlan& tp, const T* v, int64_t ldv, T* dst,
                        int64_t ldd, int64_t m, double* ws, double* r_out,
-                       int64_t r_rs, int64_t r_cs, hipStream_t st) {
+                       int64_t r_rs, int64_t r_cs, int32_t* syncs,
+                       hipStream_t st) {
   if (tp.wave)
     return launch_wave_tsqr<T>(tp, v, ldv, dst, ldd, m, ws, r_out, r_rs, r_cs,
-                               st);
+                               syncs, st);
   switch (tp.s) {
 #define TQ(S_) case S_: return launch_tsqr_s<T, S_>(tp, v, ldv, dst, ldd, m, \
-                                                    ws, r_out, r_rs, r_cs, st);
+                                                    ws, r_out, r_rs, r_cs, \
+                                                    syncs, st);
     TQ(1) TQ(2) TQ(4) TQ(8) TQ(16) TQ(32) TQ(64)
 #undef TQ
     default:
       return launch_tsqr_s<T, 0>(tp, v, ldv, dst, ldd, m, ws, r_out, r_rs,
-                                 r_cs, st);
+                                 r_cs, syncs, st);
   }
 }
 
 template hipError_t launch_tsqr<double>(const TsqrPlan&, const double*,
                                         int64_t, double*, int64_t, int64_t,
                                         double*, double*, int64_t, int64_t,
-                                        hipStream_t);
+                                        int32_t*, hipStream_t);
 template hipError_t launch_tsqr<float>(const TsqrPlan&, const float*,
                                         int64_t, float*, int64_t, int64_t,
                                         double*, double*, int64_t, int64_t,
-                                        hipStream_t);
+                                        int32_t*, hipStream_t);
 
 }  // namespace bcgs

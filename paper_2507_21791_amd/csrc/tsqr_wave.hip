@@ -292,11 +292,13 @@ template <int S>
 __global__ __launch_bounds__(256) void node_kernel(
     const double* __restrict__ rprev, int64_t nprev, int fan, int64_t nnodes,
     double* __restrict__ rcur, double* __restrict__ qcur, int is_root,
-    double* r_out, int64_t r_rs, int64_t r_cs) {
+    double* r_out, int64_t r_rs, int64_t r_cs, int32_t* syncs) {
   __shared__ double lds[4][4 * S * S];
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int64_t node = (int64_t)blockIdx.x * 4 + wv;
   if (node >= nnodes) return;
+  // the root completes the synchronization point of this TSQR
+  if (is_root && syncs != nullptr && lane == 0) *syncs += 1;
   constexpr int R = Geo<S>::R;
   const int64_t c0 = node * fan;
   const int nch = (int)min((int64_t)fan, nprev - c0);
@@ -373,7 +375,7 @@ static hipError_t launch_wave_tsqr_s(const TsqrPlan& tp, const T* v,
                                      int64_t ldv, T* dst, int64_t ldd,
                                      int64_t m, double* ws, double* r_out,
                                      int64_t r_rs, int64_t r_cs,
-                                     hipStream_t st) {
+                                     int32_t* syncs, hipStream_t st) {
   const int fan = tp.fan;
   const double ss = (double)S * S, esz = sizeof(T);
   auto wgs = [](int64_t waves) { return dim3((unsigned)cdiv(waves, 4)); };
@@ -387,7 +389,7 @@ static hipError_t launch_wave_tsqr_s(const TsqrPlan& tp, const T* v,
     hipLaunchKernelGGL(tw::node_kernel<S>, wgs(tp.nodes[l]), dim3(256), 0, st,
                        ws + tp.r_off[l - 1], tp.nodes[l - 1], fan,
                        tp.nodes[l], ws + tp.r_off[l], ws + tp.q_off[l],
-                       l == tp.levels ? 1 : 0, r_out, r_rs, r_cs);
+                       l == tp.levels ? 1 : 0, r_out, r_rs, r_cs, syncs);
     prof_end();
   }
   tsqr_down(tp, ws, st);
@@ -402,11 +404,11 @@ template <typename T>
 hipError_t launch_wave_tsqr(const TsqrPlan& tp, const T* v, int64_t ldv,
                             T* dst, int64_t ldd, int64_t m, double* ws,
                             double* r_out, int64_t r_rs, int64_t r_cs,
-                            hipStream_t st) {
+                            int32_t* syncs, hipStream_t st) {
   switch (tp.s) {
 #define TW(S_) case S_: return launch_wave_tsqr_s<T, S_>(tp, v, ldv, dst, ldd, \
                                                          m, ws, r_out, r_rs, \
-                                                         r_cs, st);
+                                                         r_cs, syncs, st);
     TW(1) TW(2) TW(3) TW(4) TW(5) TW(6) TW(7) TW(8) TW(9) TW(10) TW(11)
     TW(12) TW(13) TW(14) TW(15) TW(16)
 #undef TW
@@ -418,10 +420,12 @@ hipError_t launch_wave_tsqr(const TsqrPlan& tp, const T* v, int64_t ldv,
 template hipError_t launch_wave_tsqr<double>(const TsqrPlan&, const double*,
                                              int64_t, double*, int64_t,
                                              int64_t, double*, double*,
-                                             int64_t, int64_t, hipStream_t);
+                                             int64_t, int64_t, int32_t*,
+                                             hipStream_t);
 template hipError_t launch_wave_tsqr<float>(const TsqrPlan&, const float*,
                                              int64_t, float*, int64_t,
                                              int64_t, double*, double*,
-                                             int64_t, int64_t, hipStream_t);
+                                             int64_t, int64_t, int32_t*,
+                                             hipStream_t);
 
 }  // namespace bcgs

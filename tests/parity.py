@@ -1,6 +1,8 @@
 """Helpers for GPU-vs-oracle parity tests (imported by the GPU tests).
 
 Tolerances (binary64, u = 2^-53, n columns, kappa = kappa(X)):
+  syncs      the device's count of completed synchronization points equals
+             the oracle's count of the same variant
   status     identical; a breakdown on one side only is accepted when the
              other side's failing pivot is within 64 s u ||A|| of zero
              (a rounding-level tie at the breakdown threshold)
@@ -8,7 +10,8 @@ Tolerances (binary64, u = 2^-53, n columns, kappa = kappa(X)):
   LOO        if the oracle's ||Q^T Q - I|| <= 10 n u then the GPU's too;
              otherwise within a factor 10 of the oracle's
   residual   ||X - QR|| / ||X|| <= 10 n u
-  R          ||R_gpu - R_oracle||_F / ||R_oracle||_F <= 10 n u kappa
+  R          ||R_gpu - R_oracle||_F / ||R_oracle||_F <= 10 n u kappa, and
+             the same ratio for every block column of s columns
   Q          ||Q_gpu - Q_oracle||_F / sqrt(n) <= 10 n u kappa
 The factor 10 n u is the reading of Table 1's O(u); the kappa factor is
 the first-order perturbation bound of the QR factors.
@@ -75,6 +78,8 @@ def compare(X, s, variant, Qg, Rg, info, kappa=None, oracle_result=None):
         return {"breakdown": info.block}
     Rg = np.asarray(Rg)
     Qg = np.asarray(Qg)
+    # synchronization points counted on the device as they completed
+    assert info.syncs == r.syncs, (info.syncs, r.syncs)
     assert np.all(np.tril(Rg, -1) == 0.0), "R not upper triangular"
     assert np.all(np.diag(Rg) > 0), "diag(R) not positive"
     loo_o = O.loss_of_orthogonality(r.Q)
@@ -87,10 +92,25 @@ def compare(X, s, variant, Qg, Rg, info, kappa=None, oracle_result=None):
     assert res <= 10 * n * U64, res
     rerr = np.linalg.norm(Rg - r.R) / np.linalg.norm(r.R)
     assert rerr <= tol_pert, (rerr, tol_pert)
+    rcol = block_column_errors(Rg, r.R, s)
+    worst = int(np.argmax(rcol))
+    assert rcol[worst] <= tol_pert, (worst, rcol[worst], tol_pert)
     qerr = np.linalg.norm(Qg - r.Q) / math.sqrt(n)
     assert qerr <= tol_pert, (qerr, tol_pert)
     return {"loo_gpu": loo_g, "loo_oracle": loo_o, "res": res,
-            "r_err": rerr, "q_err": qerr}
+            "r_err": rerr, "r_col_err": float(rcol[worst]), "q_err": qerr}
+
+
+def block_column_errors(Rg, Ro, s):
+    """||R_gpu[:, K] - R_or[:, K]||_F / ||R_or[:, K]||_F for every block
+    column K (s columns): a whole-matrix ratio would hide errors in block
+    columns whose norm is far below ||R||."""
+    n = Ro.shape[1]
+    out = np.empty(n // s)
+    for k in range(n // s):
+        c = slice(k * s, (k + 1) * s)
+        out[k] = np.linalg.norm(Rg[:, c] - Ro[:, c]) / np.linalg.norm(Ro[:, c])
+    return out
 
 
 U32 = 2.0 ** -24
@@ -109,6 +129,7 @@ def compare_bulk32(X, s, variant, Qg, Rg, info, kappa):
     r = O.qr(X, s, variant)
     assert r.breakdown is None, r.breakdown
     assert info.status == 0, info.as_dict()
+    assert info.syncs == r.syncs, (info.syncs, r.syncs)
     Rg = np.asarray(Rg)
     Qg = np.asarray(Qg)
     assert np.all(np.tril(Rg, -1) == 0.0), "R not upper triangular"
@@ -120,6 +141,8 @@ def compare_bulk32(X, s, variant, Qg, Rg, info, kappa):
     assert res <= tol, (res, tol)
     rerr = np.linalg.norm(Rg - r.R) / np.linalg.norm(r.R)
     assert rerr <= tol * kappa, (rerr, tol * kappa)
+    rcol = block_column_errors(Rg, r.R, s)
+    assert rcol.max() <= tol * kappa, (int(np.argmax(rcol)), rcol.max())
     qerr = np.linalg.norm(Qg - r.Q) / math.sqrt(n)
     assert qerr <= tol * kappa, (qerr, tol * kappa)
     return {"loo_gpu": loo_g, "loo_oracle": O.loss_of_orthogonality(r.Q),

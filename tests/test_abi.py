@@ -166,6 +166,18 @@ def test_tuning_table():
     assert bcgs.tuning_get(100000, 256, 16, "p-1s")[2] is False
 
 
+@pytest.mark.parametrize("variant", ["bcgsi+", "p-2s", "p-1s", "pipi+",
+                                     "bcgsi+1s"])
+def test_tuning_set_every_variant(variant):
+    """Every variant the entry points accept can be tuned by hand too."""
+    bcgs.tuning_clear()
+    bcgs.tuning_set(50000, 64, 8, variant, max_wg=128, shape=3)
+    assert bcgs.tuning_get(50000, 64, 8, variant) == (128, 3, True)
+    bcgs.tuning_set(50000, 64, 8, variant)            # erase
+    assert bcgs.tuning_get(50000, 64, 8, variant)[2] is False
+    bcgs.tuning_clear()
+
+
 def test_queue_struct_layouts():
     assert ctypes.sizeof(bcgs.QueueConfig) == 32
     assert bcgs.QueueConfig.output_arena_bytes.offset == 16
