@@ -127,6 +127,35 @@ bcgs_status bcgs_qr_ex(const void* X, int64_t ldx, int64_t m, int64_t n,
                        size_t ws_bytes, bcgs_info* d_info,
                        hipStream_t stream);
 
+/* Size of the fixed per-device scratch array of bcgs_qr_noalloc. */
+#define BCGS_NOALLOC_SCRATCH_BYTES (64ull << 20)
+
+/* bcgs_qr_ex without any device allocation, for callers that cannot
+ * allocate: code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc.  Same arguments and results as bcgs_qr_ex (same
+ * kernels, so the same bits for the same problem), except that the
+ * workspace is a fixed device array of BCGS_NOALLOC_SCRATCH_BYTES inside
+ * the library, one per GPU, held from the first call on that GPU until the
+ * process ends.  The call makes no hipMalloc / hipFree and no allocating
+ * library call (launch profiling through bcgs_profile_start must be off on
+ * the stream).
+ *   - BCGS_ERR_NOMEM, nothing enqueued, when bcgs_workspace_size() of the
+ *     problem exceeds BCGS_NOALLOC_SCRATCH_BYTES (about m n <= 2^28 at
+ *     s = 16 fits, e.g. m = 2^20, n = 256).
+ *   - Every call on one GPU uses that GPU's one array: calls that overlap
+ *     in time on the same GPU (other streams, other threads) race and
+ *     corrupt each other's results; serialize them (one stream, or events).
+ *     A call does not depend on what an earlier call left in the array:
+ *     every value the factorization uses is written by the same call
+ *     first.
+ *   - The first call on a device resolves the array's address with that
+ *     device current (hipGetSymbolAddress); BCGS_ERR_HIP if that fails. */
+bcgs_status bcgs_qr_noalloc(const void* X, int64_t ldx, int64_t m, int64_t n,
+                            int64_t s, bcgs_variant variant,
+                            bcgs_precision precision, void* Q, int64_t ldq,
+                            double* R, int64_t ldr, bcgs_info* d_info,
+                            hipStream_t stream);
+
 /* Bytes of device workspace bcgs_qr_ex needs for this problem (0 on invalid
  * arguments).  No device call is made. */
 size_t bcgs_workspace_size(int64_t m, int64_t n, int64_t s,

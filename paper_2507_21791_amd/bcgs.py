@@ -93,6 +93,13 @@ _PROTOS = {
                                   ctypes.c_void_p, ctypes.c_int64,
                                   ctypes.c_void_p, ctypes.c_size_t,
                                   ctypes.c_void_p, ctypes.c_void_p]),
+    "bcgs_qr_noalloc": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64,
+                                       ctypes.c_int64, ctypes.c_int64,
+                                       ctypes.c_int64, ctypes.c_int,
+                                       ctypes.c_int, ctypes.c_void_p,
+                                       ctypes.c_int64, ctypes.c_void_p,
+                                       ctypes.c_int64, ctypes.c_void_p,
+                                       ctypes.c_void_p]),
     "bcgs_workspace_size": (ctypes.c_size_t, [ctypes.c_int64, ctypes.c_int64,
                                               ctypes.c_int64, ctypes.c_int,
                                               ctypes.c_int]),
@@ -229,6 +236,25 @@ def qr(X, s, variant="p-1s", precision="fp64", Q=None, R=None, ws=None,
     if st != BCGS_OK:
         raise BcgsError(st, "bcgs_qr_ex")
     return Q, R, ws
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20    # BCGS_NOALLOC_SCRATCH_BYTES
+
+
+def qr_noalloc(X, s, variant, precision, Q, R, info_buf, stream=None):
+    """bcgs_qr_noalloc: the factorization with the library's fixed device
+    scratch array as workspace (the caller passes every output: Q, R and a
+    device buffer of at least INFO_BYTES for the info record)."""
+    m, n = X.shape
+    st = lib().bcgs_qr_noalloc(
+        ctypes.c_void_p(X.data_ptr()), _col_major(X, "X"), m, n, s,
+        VARIANTS[variant], PRECISIONS[precision],
+        ctypes.c_void_p(Q.data_ptr()), _col_major(Q, "Q"),
+        ctypes.c_void_p(R.data_ptr()), _col_major(R, "R"),
+        ctypes.c_void_p(info_buf.data_ptr()), _stream_handle(stream))
+    if st != BCGS_OK:
+        raise BcgsError(st, "bcgs_qr_noalloc")
+    return Q, R
 
 
 def qr_simple(X, s, variant, Q, R, stream=None):

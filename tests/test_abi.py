@@ -107,6 +107,23 @@ def test_null_and_aliasing_rejected():
     del args
 
 
+def test_noalloc_rejects_oversize_before_enqueue():
+    """bcgs_qr_noalloc refuses a problem whose workspace exceeds its fixed
+    array, before any device call (fake pointers are never touched)."""
+    m, n, s = 1 << 22, 256, 16
+    assert bcgs.workspace_size(m, n, s, "p-1s") > bcgs.NOALLOC_SCRATCH_BYTES
+    fake = ctypes.c_void_p
+    st = bcgs.lib().bcgs_qr_noalloc(
+        fake(0x1000000000), m, m, n, s, 2, 0, fake(0x3000000000), m,
+        fake(0x5000000000), n, fake(0x6000000000), None)
+    assert st == 3      # BCGS_ERR_NOMEM: the problem does not fit the array
+    # and the usual argument checks come first
+    st = bcgs.lib().bcgs_qr_noalloc(
+        fake(0x1000000000), 10, 100, 8, 4, 2, 0, fake(0x3000000000), 100,
+        fake(0x5000000000), 8, fake(0x6000000000), None)
+    assert st == bcgs.BCGS_ERR_ARG      # ldx < m
+
+
 def test_status_strings():
     L = bcgs.lib()
     assert L.bcgs_status_string(0) == b"ok"
