@@ -67,15 +67,20 @@ def accuracy(X, Q, R, chunk=1 << 16):
 
 
 def time_variant(X, s, variant, steps, warmup, Q, R, precision="fp64"):
+    """Times `steps` factorizations with HIP events only between steps (no
+    per-launch events), then
+    the same number of steps again with the library's per-launch events on
+    the launch stream, which give the per-kernel durations the roofline
+    uses.  Returns (ms per step of the plain run, per-launch records of the
+    profiled run, info, per-step ms of the plain run, ms per step of the
+    profiled run)."""
     import torch
     from paper_2507_21791_amd import bcgs
     m, n = X.shape
     ws = bcgs.Workspace(m, n, s, variant, precision, X.device)
     for _ in range(warmup):
         bcgs.qr(X, s, variant, precision, Q=Q, R=R, ws=ws)
-    torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
-    bcgs.profile_start(stream)
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
     torch.cuda.synchronize()
     ev[0].record(stream)
@@ -83,12 +88,21 @@ def time_variant(X, s, variant, steps, warmup, Q, R, precision="fp64"):
         bcgs.qr(X, s, variant, precision, Q=Q, R=R, ws=ws)
         ev[k + 1].record(stream)
     torch.cuda.synchronize()
-    recs = bcgs.profile_stop(stream)
     ms = ev[0].elapsed_time(ev[steps]) / steps
     per_step = [ev[k].elapsed_time(ev[k + 1]) for k in range(steps)]
+    # profiled steps: per-launch HIP events on the launch stream
+    bcgs.profile_start(stream)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for k in range(steps):
+        bcgs.qr(X, s, variant, precision, Q=Q, R=R, ws=ws)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    recs = bcgs.profile_stop(stream)
+    ms_prof = e0.elapsed_time(e1) / steps
     info = ws.info()
-    time_variant.per_step = per_step
-    return ms, recs, info
+    return ms, recs, info, per_step, ms_prof
 
 
 def copy_bandwidth(nbytes=1 << 31, reps=5):
@@ -113,12 +127,15 @@ def copy_bandwidth(nbytes=1 << 31, reps=5):
 
 
 def aggregate(recs, steps):
-    """Per (kind, tag) totals per step."""
+    """Per-kernel (kind, name) totals per step.  Names come from the
+    library: the kernel and its template arguments as rocprofv3 prints
+    them, so they match the profile summaries."""
     agg = {}
     for r in recs:
-        key = (r["kind"], r["tag"])
-        a = agg.setdefault(key, {"kind": r["kind"], "tag": r["tag"], "n": 0,
-                                 "ms": 0.0, "bytes": 0.0, "flops": 0.0})
+        key = (r["kind"], r["name"])
+        a = agg.setdefault(key, {"kind": r["kind"], "name": r["name"],
+                                 "tag": r["tag"], "n": 0, "ms": 0.0,
+                                 "bytes": 0.0, "flops": 0.0})
         a["n"] += 1
         a["ms"] += r["ms"]
         a["bytes"] += r["bytes"]
@@ -127,47 +144,6 @@ def aggregate(recs, steps):
         for k in ("n", "ms", "bytes", "flops"):
             a[k] /= steps
     return sorted(agg.values(), key=lambda a: -a["ms"])
-
-
-def kernel_name(kind, tag):
-    if kind == "pass" and tag >= 1000000000:
-        # tag 1WPBSTTPPN: waves, workgroups per CU, tile buffers, both
-        # partial-sum areas, tile rows, Gram pairs per wave, B blocks
-        nw, pc = (tag // 100000000) % 10, (tag // 10000000) % 10
-        f32 = pc >= 4                    # binary32 storage
-        pc -= 4 if f32 else 0
-        nbuf, scr2 = (tag // 1000000) % 10, (tag // 100000) % 10
-        reg = nbuf >= 5                  # tiles staged through registers
-        nbuf -= 5 if reg else 0
-        tr, maxp, ntb = (tag // 1000) % 100, (tag // 10) % 100, tag % 10
-        cap = {(64, 4): 64, (64, 8): 128, (32, 4): 128, (32, 8): 272,
-               (16, 4): 272, (16, 8): 544}.get((tr, nw), 0)
-        if (tr, nw, nbuf) == (16, 4, 4):
-            cap = 272
-        if pc == 2 and scr2:
-            cap = 256
-        if f32:
-            cap = {(32, 8): 544}.get((tr, nw), 272)
-        gram = "true" if ntb else "false"
-        r = "true" if reg else "false"
-        t = "float" if f32 else "double"
-        if pc == 2:
-            k = "pass16_s2_kernel" if scr2 else "pass16_kernel"
-            return (f"{k}<{t}, {tr}, {nbuf}, {cap}, {maxp}, "
-                    f"{gram}, {max(ntb, 1)}, {r}>")
-        return (f"pass16_deep_kernel<{t}, {tr}, {nbuf}, {cap}, {nw}, "
-                f"{'true' if scr2 else 'false'}, {maxp}, {gram}, "
-                f"{max(ntb, 1)}, {r}>")
-    if kind == "pass":
-        t = "float" if tag >= 1000 else "double"
-        gram, ntb, maxa = (tag // 100) % 10, (tag // 10) % 10, tag % 10
-        return (f"pass_kernel<{t},{'true' if gram else 'false'},{ntb},"
-                f"{maxa}>")
-    return {"reduce": "gram_reduce_kernel", "epilogue": "epilogue_kernel",
-            "tsqr_leaf": "tsqr_leaf_kernel<double>",
-            "tsqr_node": "tsqr_node_kernel", "tsqr_down": "tsqr_down_kernel",
-            "tsqr_apply": "tsqr_apply_kernel<double>",
-            "other": "fill_kernel"}.get(kind, kind)
 
 
 def measured_traffic(kernel):
@@ -199,7 +175,7 @@ def by_name(agg):
     """Per-step totals of every kernel, merged by name, slowest first."""
     out = {}
     for a in agg:
-        k = kernel_name(a["kind"], a["tag"])
+        k = a["name"]
         o = out.setdefault(k, {"name": k, "launches": 0.0, "ms": 0.0,
                                "gb": 0.0, "gflop": 0.0})
         o["launches"] += a["n"]
@@ -218,13 +194,13 @@ def roofline(dom):
     t_hbm = dom["bytes"] / (HBM_PEAK_GBS * 1e9)
     t_fp = dom["flops"] / (FP64_PEAK_TFS * 1e12)
     per_launch_ms = dom["ms"] / dom["n"]
-    traffic = measured_traffic(kernel_name(dom["kind"], dom["tag"]))
+    traffic = measured_traffic(dom["name"])
     if t_fp >= t_hbm:
         achieved = dom["flops"] / dom["n"] / (per_launch_ms * 1e-3) / 1e12
         return {"bound": "mfma", "achieved": round(achieved, 3),
                 "peak": FP64_PEAK_TFS, "unit": "TFLOP/s",
                 "frac": round(achieved / FP64_PEAK_TFS, 4), "traffic": traffic,
-                "kernel": kernel_name(dom["kind"], dom["tag"]),
+                "kernel": dom["name"],
                 "launches_per_step": dom["n"],
                 "avg_launch_ms": round(per_launch_ms, 4),
                 "algorithmic_bytes": dom["bytes"] / dom["n"],
@@ -234,9 +210,21 @@ def roofline(dom):
     return {"bound": "hbm", "achieved": round(achieved, 1),
             "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-            "kernel": kernel_name(dom["kind"], dom["tag"]),
+            "kernel": dom["name"],
             "launches_per_step": dom["n"],
-            "avg_launch_ms": round(per_launch_ms, 4)}
+            "avg_launch_ms": round(per_launch_ms, 4),
+            "algorithmic_bytes": dom["bytes"] / dom["n"]}
+
+
+def cpu_model():
+    """The host CPU's model name (from /proc/cpuinfo)."""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 def cpu_baseline(Xd, s, rows, model_bytes_full, m_full):
@@ -257,7 +245,7 @@ def cpu_baseline(Xd, s, rows, model_bytes_full, m_full):
     dt = time.perf_counter() - t0
     bytes_sample = model_bytes_full * rows / m_full
     return {"value": round(bytes_sample / dt / 1e9, 3), "unit": "GB/s",
-            "cores": threads, "kind": "oracle",
+            "cores": threads, "cpu_model": cpu_model(), "kind": "oracle",
             "sample": (f"BCGSI+P-1S oracle (numpy FP64) on the first {rows} "
                        f"rows of the same X ({rows}x{Xd.shape[1]}, s={s}); "
                        f"{dt:.2f} s; GB/s under the same algorithmic byte "
@@ -278,8 +266,8 @@ def bench_fp32_bulk(m, n, s, steps, warmup, fp64_ms):
     del X64
     Q = bcgs.empty_fortran(m, n, torch.float32, "cuda")
     R = bcgs.empty_fortran(n, n, torch.float64, "cuda")
-    ms, recs, info = time_variant(X, s, "p-1s", steps, warmup, Q, R,
-                                  "fp32-bulk")
+    ms, recs, info, _, _ = time_variant(X, s, "p-1s", steps, warmup, Q, R,
+                                        "fp32-bulk")
     agg = aggregate(recs, steps)
     model_bytes = sum(a["bytes"] for a in agg)
     loo, resid = accuracy(X.double(), Q.double(), R)
@@ -294,6 +282,103 @@ def bench_fp32_bulk(m, n, s, steps, warmup, fp64_ms):
     del X, Q, R
     torch.cuda.empty_cache()
     return out
+
+
+def bench_small():
+    """The accuracy case (m = 2000, n = 80, s = 8, kappa = 1e6; seed 1):
+    LOO, residual and R against the sign-normalized Householder QR of the
+    same X (numpy/LAPACK on the host) for each variant, with the time of
+    one factorization (latency: the problem is cache resident)."""
+    import torch
+    from paper_2507_21791_amd import bcgs, workloads as W
+    w = W.WORKLOADS["small"]
+    Xh = W.make_host("small")
+    Qh, Rh = np.linalg.qr(Xh, mode="reduced")
+    d = np.where(np.diag(Rh) < 0, -1.0, 1.0)
+    Rh = d[:, None] * Rh
+    X = bcgs.empty_fortran(w["m"], w["n"], torch.float64, "cuda")
+    X.copy_(torch.from_numpy(np.asfortranarray(Xh)))
+    out = {"workload": (f"small: m={w['m']} n={w['n']} s={w['s']} "
+                        f"kappa=1e{w['decades']} FP64"), "variants": {}}
+    for v in ("bcgsi+", "p-2s", "p-1s"):
+        Q, R, ws = bcgs.qr(X, w["s"], v)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(10):
+            bcgs.qr(X, w["s"], v, Q=Q, R=R, ws=ws)
+        e1.record()
+        torch.cuda.synchronize()
+        info = ws.info()
+        loo, res = accuracy(X, Q, R)
+        rerr = float(np.linalg.norm(R.cpu().numpy() - Rh) /
+                     np.linalg.norm(Rh))
+        out["variants"][v] = {"status": info.status, "loo": loo,
+                              "residual": res, "r_vs_householder": rerr,
+                              "ms": round(e0.elapsed_time(e1) / 10, 4)}
+    log(f"[bench] small: {out}")
+    return out
+
+
+def bench_twin(steps, warmup):
+    """The kappa = 1e6 twin of the tall workload (same shape and seed):
+    time and accuracy of P-1S, P-2S and BCGSI+, where every variant meets
+    its Table 1 assumption."""
+    import torch
+    from paper_2507_21791_amd import bcgs, workloads as W
+    w = W.WORKLOADS["tall-k6"]
+    X = W.make_device("tall-k6")
+    Q = bcgs.empty_fortran(w["m"], w["n"], torch.float64, "cuda")
+    R = bcgs.empty_fortran(w["n"], w["n"], torch.float64, "cuda")
+    out = {"workload": (f"tall-k6: m={w['m']} n={w['n']} s={w['s']} "
+                        "kappa=1e6 FP64"), "variants": {}}
+    for v in ("p-1s", "p-2s", "bcgsi+"):
+        ms, recs, info, _, _ = time_variant(X, w["s"], v, steps, warmup, Q,
+                                            R)
+        gb = sum(r["bytes"] for r in recs) / steps / 1e9
+        loo, res = accuracy(X, Q, R)
+        out["variants"][v] = {"ms": round(ms, 4),
+                              "gbs": round(gb / (ms * 1e-3), 1),
+                              "status": info.status, "loo": loo,
+                              "residual": res}
+    bi = out["variants"]["bcgsi+"]["ms"]
+    out["speedups_vs_bcgsi+"] = {v: round(bi / r["ms"], 3)
+                                 for v, r in out["variants"].items()}
+    log(f"[bench] tall-k6: {out}")
+    del X, Q, R
+    torch.cuda.empty_cache()
+    return out
+
+
+def bench_sweep(steps, warmup, sizes=(4, 8, 16, 32, 64)):
+    """The block-size sweep (m = 2^20, n = 512, kappa about 1.05, seed 3):
+    time, algorithmic GB/s and TFLOP/s of P-1S, P-2S and BCGSI+ for each
+    block size s."""
+    import torch
+    from paper_2507_21791_amd import bcgs, workloads as W
+    w = W.WORKLOADS["sweep"]
+    X = W.make_device("sweep")
+    Q = bcgs.empty_fortran(w["m"], w["n"], torch.float64, "cuda")
+    R = bcgs.empty_fortran(w["n"], w["n"], torch.float64, "cuda")
+    rows = []
+    for s in sizes:
+        row = {"s": s}
+        for v in ("p-1s", "p-2s", "bcgsi+"):
+            ms, recs, info, _, _ = time_variant(X, s, v, steps, warmup, Q, R)
+            gb = sum(r["bytes"] for r in recs) / steps / 1e9
+            tf = sum(r["flops"] for r in recs) / steps / 1e12
+            row[v] = {"ms": round(ms, 3), "gbs": round(gb / (ms * 1e-3), 1),
+                      "tflops": round(tf / (ms * 1e-3), 2),
+                      "status": info.status}
+        row["p-1s_vs_bcgsi+"] = round(row["bcgsi+"]["ms"] /
+                                      row["p-1s"]["ms"], 3)
+        log(f"[bench] sweep s={s}: {row}")
+        rows.append(row)
+    del X, Q, R
+    torch.cuda.empty_cache()
+    return {"workload": (f"sweep: m={w['m']} n={w['n']} kappa~1.05 FP64, "
+                         f"{steps} timed steps each"), "rows": rows}
 
 
 def bench_batched(count, reps):
@@ -459,6 +544,10 @@ def main():
     ap.add_argument("--no-check", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-small", action="store_true")
+    ap.add_argument("--no-twin", action="store_true")
+    ap.add_argument("--no-sweep", action="store_true")
+    ap.add_argument("--sweep-steps", type=int, default=3)
     ap.add_argument("--batched-count", type=int, default=256)
     ap.add_argument("--no-served", action="store_true")
     ap.add_argument("--served-n", type=int, default=1000)
@@ -502,12 +591,14 @@ def main():
     variants = args.variants.split(",")
     for v in variants:
         log(f"[bench] timing {v}: {args.warmup} warmup + {args.steps} steps")
-        ms, recs, info = time_variant(X, s, v, args.steps, args.warmup, Q, R)
+        ms, recs, info, steps_ms, ms_prof = time_variant(
+            X, s, v, args.steps, args.warmup, Q, R)
         agg = aggregate(recs, args.steps)
         model_bytes = sum(a["bytes"] for a in agg)
         model_flops = sum(a["flops"] for a in agg)
-        steps_ms = sorted(time_variant.per_step)
+        steps_ms = sorted(steps_ms)
         res = {"ms": round(ms, 4),
+               "ms_profiled": round(ms_prof, 4),
                "step_ms_median": round(float(np.median(steps_ms)), 4),
                "step_ms_p99": round(float(np.percentile(steps_ms, 99)), 4),
                "model_gb": round(model_bytes / 1e9, 3),
@@ -574,6 +665,12 @@ def main():
     if not args.no_fp32:
         out["fp32_bulk"] = bench_fp32_bulk(m, n, s, args.steps, args.warmup,
                                            head["ms"])
+    if not args.no_small:
+        out["small"] = bench_small()
+    if not args.no_twin:
+        out["tall_k6"] = bench_twin(args.steps, args.warmup)
+    if not args.no_sweep:
+        out["sweep"] = bench_sweep(args.sweep_steps, 1)
     if not args.no_batched:
         out["batched"] = bench_batched(args.batched_count, 3)
     if not args.no_served:

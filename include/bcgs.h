@@ -293,13 +293,20 @@ bcgs_status bcgs_queue_create(const bcgs_queue_config* cfg,
  * (ld = m and n; admission waits, in arrival order, until the arena has
  * room) and returns them in the stats; the caller returns them with
  * bcgs_queue_free_output.  Never waits for the device.
+ * Ordering: `stream` is the caller's stream that produced X (and, if the
+ * caller owns them, last used Q, R and the info record).  The call records
+ * an event on it, and the request's kernels (on a queue stream) start only
+ * after everything enqueued on `stream` before the call has completed; so
+ * X may be written asynchronously right before submitting.  The caller
+ * must not touch X, Q, R or the info record again before poll or wait
+ * reports the request finished.
  * BCGS_ERR_ARG (the checks of bcgs_qr_ex, queue-allocated outputs without
  * an arena, or the queue is being destroyed), BCGS_ERR_NOMEM (the outputs
  * can never fit the arena), BCGS_ERR_QUEUE_FULL (2^20 requests waiting),
  * BCGS_ERR_HIP (an earlier request hit a runtime failure), else BCGS_OK
  * and *ticket. */
 bcgs_status bcgs_queue_submit(bcgs_queue_t q, const bcgs_problem* p,
-                              uint64_t* ticket);
+                              hipStream_t stream, uint64_t* ticket);
 
 /* Non-blocking: BCGS_PENDING (stats so far), or the final status with the
  * final stats, after which the ticket is forgotten (BCGS_ERR_ARG on an
@@ -344,15 +351,18 @@ enum {
 /* One profiled launch.  tag identifies the kernel instantiation.  For
  * BCGS_KERNEL_PASS, tags >= 10^9 are the s <= 16 pass, decimal digits
  * 1 W P B S TT PP N (waves, workgroups per CU, tile buffers, second partial
- * area, tile rows, Gram pairs per wave, Gram B blocks); smaller tags are the
- * general pass, 1000*(binary32) + 100*gram + 10*B blocks + A blocks per
- * wave. */
+ * area, tile rows, Gram pairs per wave (+50 with a compile-time update step
+ * count), Gram B blocks); smaller tags are the general pass,
+ * 1000*(binary32) + 100*gram + 10*B blocks + A blocks per wave.
+ * name: the kernel as profiler summaries print it (kernel name and
+ * template arguments, no namespace or parameter list), NUL-terminated. */
 typedef struct {
     int32_t kind;
     int32_t tag;
     double ms;
     double bytes;
     double flops;
+    char name[112];
 } bcgs_launch_record;
 
 /* Start recording launches on `stream` (host-side; no device call). */

@@ -43,7 +43,7 @@ class LaunchRecord(ctypes.Structure):
     """Mirror of bcgs_launch_record."""
     _fields_ = [("kind", ctypes.c_int32), ("tag", ctypes.c_int32),
                 ("ms", ctypes.c_double), ("bytes", ctypes.c_double),
-                ("flops", ctypes.c_double)]
+                ("flops", ctypes.c_double), ("name", ctypes.c_char * 112)]
 
 
 class Problem(ctypes.Structure):
@@ -121,6 +121,7 @@ _PROTOS = {
     "bcgs_tuning_clear": (None, []),
     "bcgs_queue_create": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "bcgs_queue_submit": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p,
+                                         ctypes.c_void_p,
                                          ctypes.c_void_p]),
     "bcgs_queue_poll": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64,
                                        ctypes.c_void_p]),
@@ -274,13 +275,14 @@ def profile_start(stream=None):
 
 def profile_stop(stream=None, capacity=1 << 16):
     """Stop profiling the stream; returns a list of launch dicts
-    (kind, tag, ms, bytes, flops) in launch order."""
+    (kind, tag, name, ms, bytes, flops) in launch order."""
     recs = (LaunchRecord * capacity)()
     n = lib().bcgs_profile_stop(_stream_handle(stream), recs, capacity)
     if n < 0:
         raise BcgsError(BCGS_ERR_ARG, "bcgs_profile_stop")
     return [{"kind": KERNEL_KINDS.get(r.kind, r.kind), "tag": r.tag,
-             "ms": r.ms, "bytes": r.bytes, "flops": r.flops}
+             "name": r.name.decode(), "ms": r.ms, "bytes": r.bytes,
+             "flops": r.flops}
             for r in recs[:min(n, capacity)]]
 
 
@@ -396,12 +398,15 @@ class Queue:
         self.live = {}
 
     def submit(self, X, s, variant="p-1s", precision="fp64", Q=None, R=None,
-               outputs="caller"):
+               outputs="caller", stream=None):
         """Submit X = QR; returns the ticket.  outputs="caller": Q and R are
         torch tensors (allocated here when not given); outputs="queue": the
         queue carves them out of its output arena at admission and the
-        result carries their device pointers (return them with free()).  The tensors and a device
-        info record stay alive until the request is collected."""
+        result carries their device pointers (return them with free()).
+        The tensors and a device info record stay alive until the request
+        is collected.  The request runs after everything enqueued so far on
+        `stream` (the current stream by default), which may still be
+        writing X."""
         import torch
         m, n = X.shape
         ldx = _col_major(X, "X")
@@ -427,7 +432,7 @@ class Queue:
                        info.data_ptr())
         t = ctypes.c_uint64()
         st = lib().bcgs_queue_submit(self.handle, ctypes.byref(prob),
-                                     ctypes.byref(t))
+                                     _stream_handle(stream), ctypes.byref(t))
         if st != BCGS_OK:
             raise BcgsError(st, "bcgs_queue_submit")
         self.live[t.value] = (X, Q, R, info)

@@ -215,5 +215,12 @@ void prof_attach(hipStream_t st);
 void prof_detach();
 void prof_begin(int kind, int tag, double bytes, double flops);
 void prof_end();
+// Names the launch being recorded (printf-style; a no-op unless profiling
+// is active) in the short form profiler summaries print: the kernel's name
+// and template arguments, without namespaces or parameter list.
+void prof_name(const char* fmt, ...) __attribute__((format(printf, 1, 2)));
+template <typename T>
+constexpr const char* type_name() { return sizeof(T) == 8 ? "double" : "float"; }
+constexpr const char* bool_name(bool b) { return b ? "true" : "false"; }
 
 }  // namespace bcgs

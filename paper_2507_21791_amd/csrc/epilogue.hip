@@ -754,12 +754,14 @@ hipError_t launch_epilogue(const EpiArgs& a, hipStream_t st) {
   prof_begin(BCGS_KERNEL_EPILOGUE, a.mode * 1000 + a.j, 0.0, 0.0);
   switch (a.s) {
 #define EPI(S_) case S_: hipLaunchKernelGGL(epilogue_kernel<S_>, dim3(1), \
-                                            dim3(kThreads), 0, st, a); break;
+                                            dim3(kThreads), 0, st, a); \
+                         prof_name("epilogue_kernel<%d>", S_); break;
     EPI(4) EPI(8) EPI(16) EPI(32)
 #undef EPI
     default:
       hipLaunchKernelGGL(epilogue_kernel<0>, dim3(1), dim3(kThreads), 0, st,
                          a);
+      prof_name("epilogue_kernel<0>");
   }
   prof_end();
   return hipGetLastError();
@@ -780,6 +782,7 @@ hipError_t launch_fill(double* p, int64_t rows, int64_t cols, int64_t ld,
   prof_begin(BCGS_KERNEL_OTHER, 0, 8.0 * rows * cols, 0.0);
   hipLaunchKernelGGL(fill_kernel, dim3((unsigned)cdiv(rows * cols, 256)),
                      dim3(256), 0, st, p, rows, cols, ld, value);
+  prof_name("fill_kernel");
   prof_end();
   return hipGetLastError();
 }

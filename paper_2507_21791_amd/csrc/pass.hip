@@ -301,6 +301,7 @@ hipError_t launch_gram_reduce(const double* partial, int G, int64_t elems,
   hipLaunchKernelGGL(gram_reduce_kernel, dim3((unsigned)blocks),
                      dim3(kRedWaves * 64), 0, st, partial, G, elems, out,
                      syncs);
+  prof_name("gram_reduce_kernel");
   prof_end();
   return hipGetLastError();
 }
@@ -330,6 +331,8 @@ static hipError_t launch_one(const PassArgs<T>& a, int G, hipStream_t st,
   }
   hipLaunchKernelGGL(kern, dim3((unsigned)(G * a.groups)), dim3(kThreads),
                      lds, st, a);
+  prof_name("pass_kernel<%s, %s, %d, %d>", type_name<T>(), bool_name(GRAM),
+            NTB, MAXA);
   return hipGetLastError();
 }
 

@@ -207,7 +207,7 @@ __device__ __forceinline__ void combine(const ArgsT<T>& a, T* tile,
 // while tile t+1 is in registers; then tile t+1 goes to the other buffer
 // and the loads of tile t+2 are issued.
 template <typename T, int TR, int NBUF, int CAP, int PC, int NW, bool SCR2,
-          int MAXP, bool GRAM, int NTB, bool REG>
+          int MAXP, bool GRAM, int NTB, bool REG, int KS>
 struct Kernel {
   typedef ArgsT<T> Args;
   typedef typename Elt<T>::V16 V16;
@@ -223,6 +223,7 @@ struct Kernel {
   static constexpr int TE = CAP * TR;         // elements per buffer
   static_assert(CAP % CPI == 0, "buffer holds whole copy instructions");
   static_assert(KG >= 1, "at least one wave per row block");
+  static_assert(KS % 2 == 0 && KS <= KF, "update steps: even, in registers");
 
   // register-resident state of one wave
   struct State {
@@ -232,43 +233,71 @@ struct Kernel {
     int mb, kg;
     T acc[MAXP][4];
     int npairs;
+    bool fast;                         // uniform-base tile copies
   };
 
-  // direct-to-LDS copy of the full tile at rows r0 .. r0+TR-1
-  static __device__ __forceinline__ void dma(const Args& a, T* buf,
-                                             int64_t r0) {
+  // Source of copy instruction i of this wave for the tile at row r0.
+  // Fast form (S.fast: every instruction's CPI columns lie in one source
+  // block, and the lane offsets fit 32 bits): the block's address at row
+  // r0 is wave-uniform (scalar registers) and each lane adds a 32-bit
+  // offset (its column times the leading dimension plus its swizzled
+  // granule), so a tile costs a few instructions per copy instead of a
+  // per-lane search of the three source blocks.
+  static __device__ __forceinline__ const T* copy_src(const Args& a,
+                                                      const State& S, int i,
+                                                      int64_t r0) {
     constexpr int kGran = TR / E;                    // granules per column
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int ninst = (a.ncols + CPI - 1) / CPI;
-#pragma unroll
-    for (int i = 0; i < IPW; ++i) {
-      const int ins = min(wave + NW * i, ninst - 1);
-      const int c = ins * CPI + lane / kGran;
-      const int g = lane % kGran;
+    const int ins = min(wave + NW * i, ninst - 1);
+    const int lc = lane / kGran, g = lane % kGran;
+    if (S.fast) {
+      const int c0 = ins * CPI;
+      const T* base;
       int64_t ld;
-      const T* src = col_ptr(a, min(c, a.ncols - 1), &ld);
-      const int rr = (g ^ swz<T, TR>(c)) * E;
-      __builtin_amdgcn_global_load_lds(src + r0 + rr, buf + ins * CPI * TR,
-                                       16, 0, 0);
+      int cl;
+      if (c0 < a.nq) {
+        base = a.q; ld = a.ldq; cl = c0;
+      } else if (c0 < a.nq + a.fcols) {
+        base = a.f; ld = a.ldf; cl = c0 - a.nq;
+      } else {
+        base = a.e; ld = a.lde; cl = c0 - a.nq - a.fcols;
+      }
+      const T* sb = base + (int64_t)cl * ld + r0;
+      const uint32_t off = (uint32_t)lc * (uint32_t)ld +
+                           (uint32_t)((g ^ swz<T, TR>(c0 + lc)) * E);
+      return sb + off;
     }
+    const int c = ins * CPI + lc;
+    int64_t ld;
+    const T* src = col_ptr(a, min(c, a.ncols - 1), &ld);
+    return src + r0 + (g ^ swz<T, TR>(c)) * E;
+  }
+
+  // LDS offset (elements) of copy instruction i of this wave in a buffer
+  static __device__ __forceinline__ int copy_dst(const Args& a, int i) {
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int ninst = (a.ncols + CPI - 1) / CPI;
+    return min(wave + NW * i, ninst - 1) * CPI * TR;
+  }
+
+  // direct-to-LDS copy of the full tile at rows r0 .. r0+TR-1
+  static __device__ __forceinline__ void dma(const Args& a, const State& S,
+                                             T* buf, int64_t r0) {
+#pragma unroll
+    for (int i = 0; i < IPW; ++i)
+      __builtin_amdgcn_global_load_lds(copy_src(a, S, i, r0),
+                                       buf + copy_dst(a, i), 16, 0, 0);
   }
 
   // register staging: the loads of the tile at rows r0 .. r0+TR-1
-  static __device__ __forceinline__ void issue(const Args& a, int64_t r0,
+  static __device__ __forceinline__ void issue(const Args& a, const State& S,
+                                               int64_t r0,
                                                V16 (&pend)[IPW]) {
-    constexpr int kGran = TR / E;
-    const int lane = threadIdx.x & 63;
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int ninst = (a.ncols + CPI - 1) / CPI;
 #pragma unroll
     for (int i = 0; i < IPW; ++i) {
-      const int ins = min(wave + NW * i, ninst - 1);
-      const int c = ins * CPI + lane / kGran;
-      const int g = lane % kGran;
-      int64_t ld;
-      const T* src = col_ptr(a, min(c, a.ncols - 1), &ld);
-      const T* p = src + r0 + (g ^ swz<T, TR>(c)) * E;
+      const T* p = copy_src(a, S, i, r0);
       if constexpr (E == 2) {
         pend[i].x = p[0];
         pend[i].y = p[1];
@@ -285,13 +314,9 @@ struct Kernel {
   static __device__ __forceinline__ void commit(const Args& a, T* buf,
                                                 const V16 (&pend)[IPW]) {
     const int lane = threadIdx.x & 63;
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int ninst = (a.ncols + CPI - 1) / CPI;
 #pragma unroll
-    for (int i = 0; i < IPW; ++i) {
-      const int ins = min(wave + NW * i, ninst - 1);
-      *reinterpret_cast<V16*>(buf + ins * CPI * TR + E * lane) = pend[i];
-    }
+    for (int i = 0; i < IPW; ++i)
+      *reinterpret_cast<V16*>(buf + copy_dst(a, i) + E * lane) = pend[i];
   }
 
   // block updates of one tile (U1: update 1, U2: update 2 present), with
@@ -315,21 +340,40 @@ struct Kernel {
     Acc acc1b = {0, 0, 0, 0}, acc2b = {0, 0, 0, 0};
     const int kcl = max(S.kb, S.ke - 1);
     const int row = S.mb * 16 + li;
+    if constexpr (KS > 0) {
+      // a compile-time step count (the launcher guarantees ke - kb <= KS):
+      // no branches, so every fragment load of the tile is issued before
+      // the first MFMA waits on one
+      T av[KS];
 #pragma unroll
-    for (int q = 0; q < KF / CH; ++q) {
-      if (CH * q >= S.ke - S.kb) break;           // wave-uniform
-      T av[CH];
-#pragma unroll
-      for (int u = 0; u < CH; ++u) {
-        const int k = min(S.kb + CH * q + u, kcl);
+      for (int u = 0; u < KS; ++u) {
+        const int k = min(S.kb + u, kcl);
         av[u] = tile[at<T, TR>(4 * k + lk, row)];
       }
 #pragma unroll
-      for (int u = 0; u < CH; u += 2) {
-        if (U1) acc1 = mfma16(av[u], S.c1f[CH * q + u], acc1);
-        if (U2) acc2 = mfma16(av[u], S.c2f[CH * q + u], acc2);
-        if (U1) acc1b = mfma16(av[u + 1], S.c1f[CH * q + u + 1], acc1b);
-        if (U2) acc2b = mfma16(av[u + 1], S.c2f[CH * q + u + 1], acc2b);
+      for (int u = 0; u < KS; u += 2) {
+        if (U1) acc1 = mfma16(av[u], S.c1f[u], acc1);
+        if (U2) acc2 = mfma16(av[u], S.c2f[u], acc2);
+        if (U1) acc1b = mfma16(av[u + 1], S.c1f[u + 1], acc1b);
+        if (U2) acc2b = mfma16(av[u + 1], S.c2f[u + 1], acc2b);
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < KF / CH; ++q) {
+        if (CH * q >= S.ke - S.kb) break;           // wave-uniform
+        T av[CH];
+#pragma unroll
+        for (int u = 0; u < CH; ++u) {
+          const int k = min(S.kb + CH * q + u, kcl);
+          av[u] = tile[at<T, TR>(4 * k + lk, row)];
+        }
+#pragma unroll
+        for (int u = 0; u < CH; u += 2) {
+          if (U1) acc1 = mfma16(av[u], S.c1f[CH * q + u], acc1);
+          if (U2) acc2 = mfma16(av[u], S.c2f[CH * q + u], acc2);
+          if (U1) acc1b = mfma16(av[u + 1], S.c1f[CH * q + u + 1], acc1b);
+          if (U2) acc2b = mfma16(av[u + 1], S.c2f[CH * q + u + 1], acc2b);
+        }
       }
     }
     if (U2) {
@@ -440,7 +484,7 @@ struct Kernel {
         // has).  Otherwise idle slots are skipped by branches: with more
         // slots the operands would not fit the registers, and with one B
         // block many waves would idle a slot.
-        constexpr bool kBranchFree = NTB == 2 && MAXP <= 7;
+        constexpr bool kBranchFree = NTB == 2 && MAXP <= 8;
 #pragma unroll
         for (int i = 0; i < MAXP; ++i) {
           const int p0 = wave + NW * i;
@@ -469,7 +513,7 @@ struct Kernel {
                                               int64_t ts, int64_t t) {
     __builtin_amdgcn_s_waitcnt(P16_VM((NBUF - 2) * IPW));
     lds_barrier();
-    dma(a, bufs[(I + NBUF - 1) % NBUF], row0 + (t + NBUF - 1) * ts);
+    dma(a, S, bufs[(I + NBUF - 1) % NBUF], row0 + (t + NBUF - 1) * ts);
     process(a, S, bufs[I], scr, row0 + t * ts, TR);
   }
 
@@ -485,7 +529,7 @@ struct Kernel {
                                                   V16 (&pend)[IPW]) {
     process(a, S, bufs[I], scr, row0 + t * ts, TR);
     if (t + 1 < nfull) commit(a, bufs[I ^ 1], pend);
-    if (t + 2 < nfull) issue(a, row0 + (t + 2) * ts, pend);
+    if (t + 2 < nfull) issue(a, S, row0 + (t + 2) * ts, pend);
     lds_barrier();
   }
 
@@ -533,6 +577,13 @@ struct Kernel {
     }
 
     State S;
+    {
+      // every copy instruction within one source block, 32-bit lane offsets
+      const int64_t ldm = max(a.ldq, max(a.fcols ? a.ldf : 0,
+                                         a.ecols ? a.lde : 0));
+      S.fast = a.nq % CPI == 0 && a.fcols % CPI == 0 && a.ecols % CPI == 0 &&
+               ldm * CPI + TR < (int64_t(1) << 31);
+    }
     S.mb = wave % MB;
     S.kg = wave / MB;
     // ---- coefficient fragments.  Update 1 runs over the staged columns
@@ -585,10 +636,10 @@ struct Kernel {
       static_assert(NBUF == 2, "register staging uses two buffers");
       V16 pend[IPW];
       if (nfull >= 1) {
-        issue(a, row_begin, pend);
+        issue(a, S, row_begin, pend);
         commit(a, b0, pend);
       }
-      if (nfull >= 2) issue(a, row_begin + ts, pend);
+      if (nfull >= 2) issue(a, S, row_begin + ts, pend);
       lds_barrier();
       for (; t + 1 < nfull; t += 2) {
         step_reg<0>(a, S, bufs, scr, row_begin, ts, t, nfull, pend);
@@ -602,7 +653,7 @@ struct Kernel {
     } else if (nfull >= 2 * NBUF - 1) {
 #pragma unroll
       for (int i = 0; i < NBUF - 1; ++i)
-        dma(a, bufs[i], row_begin + i * ts);
+        dma(a, S, bufs[i], row_begin + i * ts);
       for (; t + 2 * NBUF - 2 < nfull; t += NBUF) {
         step<0>(a, S, bufs, scr, row_begin, ts, t);
         step<1>(a, S, bufs, scr, row_begin, ts, t + 1);
@@ -615,7 +666,7 @@ struct Kernel {
     for (; t < nfull; ++t) {
       const int bi = (int)(t % NBUF);
       T* tile = bi == 0 ? b0 : bi == 1 ? b1 : bi == 2 ? b2 : b3;
-      if (t >= issued) dma(a, tile, row_begin + t * ts);
+      if (t >= issued) dma(a, S, tile, row_begin + t * ts);
       __builtin_amdgcn_s_waitcnt(0);
       lds_barrier();
       process(a, S, tile, scr, row_begin + t * ts, TR);
@@ -658,19 +709,19 @@ struct Kernel {
 
 // two 4-wave workgroups per CU: at most 256 registers per lane
 template <typename T, int TR, int NBUF, int CAP, int MAXP, bool GRAM, int NTB,
-          bool REG>
+          bool REG, int KS>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
 void pass16_kernel(ArgsT<T> a) {
-  Kernel<T, TR, NBUF, CAP, 2, 4, false, MAXP, GRAM, NTB, REG>::run(a);
+  Kernel<T, TR, NBUF, CAP, 2, 4, false, MAXP, GRAM, NTB, REG, KS>::run(a);
 }
 
 // the same with both partial-sum areas (one combine round fewer per tile
 // when a pass has both block updates)
 template <typename T, int TR, int NBUF, int CAP, int MAXP, bool GRAM, int NTB,
-          bool REG>
+          bool REG, int KS>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
 void pass16_s2_kernel(ArgsT<T> a) {
-  Kernel<T, TR, NBUF, CAP, 2, 4, true, MAXP, GRAM, NTB, REG>::run(a);
+  Kernel<T, TR, NBUF, CAP, 2, 4, true, MAXP, GRAM, NTB, REG, KS>::run(a);
 }
 
 // one workgroup of NW waves per CU
@@ -678,31 +729,40 @@ template <typename T, int TR, int NBUF, int CAP, int NW, bool SCR2, int MAXP,
           bool GRAM, int NTB, bool REG>
 __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(NW / 4)))
 void pass16_deep_kernel(ArgsT<T> a) {
-  Kernel<T, TR, NBUF, CAP, 1, NW, SCR2, MAXP, GRAM, NTB, REG>::run(a);
+  Kernel<T, TR, NBUF, CAP, 1, NW, SCR2, MAXP, GRAM, NTB, REG, 0>::run(a);
 }
 
 template <typename T, int TR, int NBUF, int CAP, int PC, int NW, bool SCR2,
-          int MAXP, bool GRAM, int NTB, bool REG>
+          int MAXP, bool GRAM, int NTB, bool REG, int KS = 0>
 static hipError_t go(const ArgsT<T>& a, int G, hipStream_t st, int* tag) {
   // 1 W P B S TT PP N: waves, workgroups per CU (+4 for binary32), tile
   // buffers (+5 with register staging), both partial-sum areas, tile rows
-  // (mod 100), Gram pairs per wave, B blocks (0: no Gram)
+  // (mod 100), Gram pairs per wave (+50 with a compile-time update step
+  // count), B blocks (0: no Gram)
   *tag = 1000000000 + NW * 100000000 +
          (PC + (sizeof(T) == 4 ? 4 : 0)) * 10000000 +
          (NBUF + (REG ? 5 : 0)) * 1000000 + (SCR2 ? 100000 : 0) +
-         (TR % 100) * 1000 + MAXP * 10 + (GRAM ? NTB : 0);
-  if constexpr (PC == 2 && SCR2)
-    hipLaunchKernelGGL(
-        (pass16_s2_kernel<T, TR, NBUF, CAP, MAXP, GRAM, NTB, REG>),
-        dim3((unsigned)G), dim3(256), 0, st, a);
-  else if constexpr (PC == 2)
-    hipLaunchKernelGGL(
-        (pass16_kernel<T, TR, NBUF, CAP, MAXP, GRAM, NTB, REG>),
-        dim3((unsigned)G), dim3(256), 0, st, a);
-  else
+         (TR % 100) * 1000 + (MAXP + (KS ? 50 : 0)) * 10 + (GRAM ? NTB : 0);
+  if constexpr (PC == 2) {
+    if constexpr (SCR2)
+      hipLaunchKernelGGL(
+          (pass16_s2_kernel<T, TR, NBUF, CAP, MAXP, GRAM, NTB, REG, KS>),
+          dim3((unsigned)G), dim3(256), 0, st, a);
+    else
+      hipLaunchKernelGGL(
+          (pass16_kernel<T, TR, NBUF, CAP, MAXP, GRAM, NTB, REG, KS>),
+          dim3((unsigned)G), dim3(256), 0, st, a);
+    prof_name("%s<%s, %d, %d, %d, %d, %s, %d, %s, %d>",
+              SCR2 ? "pass16_s2_kernel" : "pass16_kernel", type_name<T>(), TR,
+              NBUF, CAP, MAXP, bool_name(GRAM), NTB, bool_name(REG), KS);
+  } else {
     hipLaunchKernelGGL(
         (pass16_deep_kernel<T, TR, NBUF, CAP, NW, SCR2, MAXP, GRAM, NTB, REG>),
         dim3((unsigned)G), dim3(NW * 64), 0, st, a);
+    prof_name("pass16_deep_kernel<%s, %d, %d, %d, %d, %s, %d, %s, %d, %s>",
+              type_name<T>(), TR, NBUF, CAP, NW, bool_name(SCR2), MAXP,
+              bool_name(GRAM), NTB, bool_name(REG));
+  }
   return hipGetLastError();
 }
 
@@ -758,36 +818,50 @@ static bool shape_fits(const Shape& sh, int ncols_p, int shared_ksteps,
 
 // Gram launch with the smallest instantiated pair count per wave M >= maxp:
 // every count from 2 up to the most pairs a wave of this shape can get (NTB
-// B blocks), at most 9.
+// B blocks), at most 9.  With two B blocks on a 16-row 4-wave shape, a pass
+// whose block-update K-steps per wave fit 2 M - 2 (the one-sync passes: j
+// steps for j + 2 staged blocks) takes the form with that compile-time step
+// count (ks).
 template <typename T, int TR, int NBUF, int CAP, int PC, int NW, bool SCR2,
           bool REG, int NTB, int M>
-static hipError_t go_maxp(const ArgsT<T>& a, int G, int maxp, hipStream_t st,
-                          int* tag) {
+static hipError_t go_maxp(const ArgsT<T>& a, int G, int maxp, bool ks,
+                          hipStream_t st, int* tag) {
   constexpr int kTop = ((CAP / 16) * NTB + NW - 1) / NW;
+  constexpr bool kKs = NTB == 2 && TR == 16 && NW == 4 && sizeof(T) == 8 &&
+                       2 * M - 2 >= 2 && 2 * M - 2 <= kf_of<T>(CAP);
   if constexpr (M >= kTop || M >= 9) {
+    if constexpr (kKs)
+      if (ks)
+        return go<T, TR, NBUF, CAP, PC, NW, SCR2, M, true, NTB, REG,
+                  2 * M - 2>(a, G, st, tag);
     return go<T, TR, NBUF, CAP, PC, NW, SCR2, M, true, NTB, REG>(a, G, st,
                                                                  tag);
   } else {
-    if (maxp <= M)
+    if (maxp <= M) {
+      if constexpr (kKs)
+        if (ks)
+          return go<T, TR, NBUF, CAP, PC, NW, SCR2, M, true, NTB, REG,
+                    2 * M - 2>(a, G, st, tag);
       return go<T, TR, NBUF, CAP, PC, NW, SCR2, M, true, NTB, REG>(a, G, st,
                                                                    tag);
+    }
     return go_maxp<T, TR, NBUF, CAP, PC, NW, SCR2, REG, NTB, M + 1>(
-        a, G, maxp, st, tag);
+        a, G, maxp, ks, st, tag);
   }
 }
 
 template <typename T, int TR, int NBUF, int CAP, int PC, int NW, bool SCR2,
           bool REG>
 static hipError_t go_shape(const ArgsT<T>& a, int G, bool gram, int ntb,
-                           int maxp, hipStream_t st, int* tag) {
+                           int maxp, bool ks, hipStream_t st, int* tag) {
   if (!gram)
     return go<T, TR, NBUF, CAP, PC, NW, SCR2, 1, false, 1, REG>(a, G, st,
                                                                 tag);
   if (ntb == 1)
-    return go_maxp<T, TR, NBUF, CAP, PC, NW, SCR2, REG, 1, 2>(a, G, maxp, st,
-                                                              tag);
-  return go_maxp<T, TR, NBUF, CAP, PC, NW, SCR2, REG, 2, 2>(a, G, maxp, st,
-                                                            tag);
+    return go_maxp<T, TR, NBUF, CAP, PC, NW, SCR2, REG, 1, 2>(a, G, maxp,
+                                                              false, st, tag);
+  return go_maxp<T, TR, NBUF, CAP, PC, NW, SCR2, REG, 2, 2>(a, G, maxp, ks,
+                                                            st, tag);
 }
 
 // Launch shape `pick` of the storage type's list (REG: register-staged
@@ -795,8 +869,9 @@ static hipError_t go_shape(const ArgsT<T>& a, int G, bool gram, int ntb,
 // pass16_f32.hip.
 template <typename T, bool REG>
 hipError_t dispatch(int pick, const ArgsT<T>& a, int G, bool gram, int ntb,
-                    int maxp, hipStream_t st, int* tag) {
-#define GS(...) go_shape<T, __VA_ARGS__, REG>(a, G, gram, ntb, maxp, st, tag)
+                    int maxp, bool ks, hipStream_t st, int* tag) {
+#define GS(...) \
+  go_shape<T, __VA_ARGS__, REG>(a, G, gram, ntb, maxp, ks, st, tag)
   if constexpr (sizeof(T) == 8) {
     switch (pick) {
       case 0: return GS(64, 2, 64, 2, 4, false);
@@ -823,7 +898,7 @@ hipError_t dispatch(int pick, const ArgsT<T>& a, int G, bool gram, int ntb,
 
 #define P16_DISPATCH_DECL(T_, R_)                                          \
   hipError_t dispatch<T_, R_>(int, const ArgsT<T_>&, int, bool, int, int, \
-                              hipStream_t, int*)
+                              bool, hipStream_t, int*)
 extern template P16_DISPATCH_DECL(double, false);
 extern template P16_DISPATCH_DECL(double, true);
 extern template P16_DISPATCH_DECL(float, false);
@@ -922,8 +997,13 @@ hipError_t launch_pass16_t(const PassArgs<T>& pa, int64_t m,
   a.partial = pa.partial;
   *G_out = G;
   const bool gram = pa.gram;
-  return reg ? dispatch<T, true>(pick, a, G, gram, ntb, maxp, st, tag)
-             : dispatch<T, false>(pick, a, G, gram, ntb, maxp, st, tag);
+  // compile-time update step count: K-steps per wave within 2 maxp - 2
+  const int kg = sh.nw / (sh.tr / 16);
+  const int per = (shared + kg - 1) / kg;
+  const bool ks = gram && ntb == 2 && (pa.upd1 || pa.upd2) && per >= 1 &&
+                  per <= 2 * maxp - 2;
+  return reg ? dispatch<T, true>(pick, a, G, gram, ntb, maxp, ks, st, tag)
+             : dispatch<T, false>(pick, a, G, gram, ntb, maxp, ks, st, tag);
 }
 
 }  // namespace p16

@@ -2,8 +2,14 @@
 // enqueues on a stream, each tagged with the launch's algorithmic HBM bytes
 // and flops (the work the method itself requires, not what the kernel
 // happens to move), so callers can compute achieved rates per kernel.
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
 #include <map>
 #include <mutex>
+#include <set>
+#include <string>
 #include <vector>
 
 #include "common.h"
@@ -14,6 +20,7 @@ struct ProfRec {
   int kind, tag;
   hipEvent_t a, b;
   double bytes, flops;
+  const char* name;      // interned (see prof_name), or null
 };
 
 struct Prof {
@@ -47,7 +54,7 @@ void prof_detach() { t_cur = nullptr; }
 void prof_begin(int kind, int tag, double bytes, double flops) {
   Prof* p = t_cur;
   if (!p) return;
-  ProfRec r{kind, tag, take_event(p), take_event(p), bytes, flops};
+  ProfRec r{kind, tag, take_event(p), take_event(p), bytes, flops, nullptr};
   if (r.a) (void)hipEventRecord(r.a, p->st);
   p->recs.push_back(r);
 }
@@ -55,6 +62,22 @@ void prof_begin(int kind, int tag, double bytes, double flops) {
 void prof_retag(int tag) {
   Prof* p = t_cur;
   if (p && !p->recs.empty()) p->recs.back().tag = tag;
+}
+
+// names live for the whole process, so records keep plain pointers
+static std::mutex g_nmu;
+static std::set<std::string> g_names;
+
+void prof_name(const char* fmt, ...) {
+  Prof* p = t_cur;
+  if (!p || p->recs.empty()) return;
+  char buf[256];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  std::lock_guard<std::mutex> lock(g_nmu);
+  p->recs.back().name = g_names.insert(buf).first->c_str();
 }
 
 void prof_end() {
@@ -102,6 +125,8 @@ int32_t bcgs_profile_stop(hipStream_t stream, bcgs_launch_record* out,
       out[n].ms = ms;
       out[n].bytes = r.bytes;
       out[n].flops = r.flops;
+      memset(out[n].name, 0, sizeof out[n].name);
+      if (r.name) strncpy(out[n].name, r.name, sizeof out[n].name - 1);
     }
     ++n;
   }

@@ -54,6 +54,7 @@ struct Request {
   bool own = false;        // Q and R allocated by the queue at admission
   bool placed = false;     // queue-allocated outputs already assigned
   bool done = false;
+  hipEvent_t ready = nullptr;  // recorded on the submitter's stream
   bcgs_request_stats stats{};
 };
 
@@ -186,6 +187,9 @@ bcgs_status start_on(Slot& sl, Request& rq) {
     sl.ws_bytes = rq.plan.bytes;
   }
   const bcgs_problem& p = rq.prob;
+  // the submitter's work on X (and on its own outputs) comes first
+  if (rq.ready && hipStreamWaitEvent(sl.stream, rq.ready, 0) != hipSuccess)
+    return BCGS_ERR_HIP;
   bcgs_status st = run_problem(rq.plan, p.X, p.ldx, p.Q, p.ldq, p.R, p.ldr,
                                sl.ws, p.d_info, sl.stream);
   if (st != BCGS_OK) return st;
@@ -393,7 +397,7 @@ bcgs_status bcgs_queue_create(const bcgs_queue_config* cfg,
 }
 
 bcgs_status bcgs_queue_submit(bcgs_queue_t q, const bcgs_problem* p,
-                              uint64_t* ticket) {
+                              hipStream_t stream, uint64_t* ticket) {
   if (!q || !p || !ticket) return BCGS_ERR_ARG;
   Request rq;
   rq.prob = *p;
@@ -418,10 +422,24 @@ bcgs_status bcgs_queue_submit(bcgs_queue_t q, const bcgs_problem* p,
       c.ldr, c.d_info, &rq.plan);
   if (st != BCGS_OK) return st;
   rq.footprint = footprint_of(c, rq.plan);
+  {
+    std::lock_guard<std::mutex> lock(q->mu);
+    if (q->stop) return BCGS_ERR_ARG;
+    if (q->fault != BCGS_OK) return q->fault;
+    if (q->waiting.size() >= kMaxWaiting) return BCGS_ERR_QUEUE_FULL;
+    if (!q->spare_events.empty()) {
+      rq.ready = q->spare_events.back();
+      q->spare_events.pop_back();
+    }
+  }
+  if (!rq.ready && hipEventCreateWithFlags(&rq.ready, hipEventDisableTiming) !=
+                       hipSuccess)
+    return BCGS_ERR_HIP;
+  if (hipEventRecord(rq.ready, stream) != hipSuccess) {
+    (void)hipEventDestroy(rq.ready);
+    return BCGS_ERR_HIP;
+  }
   std::lock_guard<std::mutex> lock(q->mu);
-  if (q->stop) return BCGS_ERR_ARG;
-  if (q->fault != BCGS_OK) return q->fault;
-  if (q->waiting.size() >= kMaxWaiting) return BCGS_ERR_QUEUE_FULL;
   rq.stats.status = BCGS_PENDING;
   rq.stats.variant = p->variant;
   rq.stats.attempts = 0;
@@ -446,6 +464,7 @@ bcgs_status bcgs_queue_poll(bcgs_queue_t q, uint64_t ticket,
     return BCGS_PENDING;
   }
   const bcgs_status st = it->second.stats.status;
+  if (it->second.ready) q->spare_events.push_back(it->second.ready);
   q->reqs.erase(it);
   return st;
 }
@@ -459,6 +478,7 @@ bcgs_status bcgs_queue_wait(bcgs_queue_t q, uint64_t ticket,
   q->cv_done.wait(lock, [&] { return it->second.done; });
   *out = it->second.stats;
   const bcgs_status st = it->second.stats.status;
+  if (it->second.ready) q->spare_events.push_back(it->second.ready);
   q->reqs.erase(it);
   return st;
 }
@@ -516,6 +536,8 @@ bcgs_status bcgs_queue_destroy(bcgs_queue_t q) {
     (void)hipEventDestroy(pf.ev);
   }
   for (hipEvent_t ev : q->spare_events) (void)hipEventDestroy(ev);
+  for (auto& kv : q->reqs)
+    if (kv.second.ready) (void)hipEventDestroy(kv.second.ready);
   if (q->out_base) (void)hipFree(q->out_base);
   (void)hipSetDevice(prev);
   delete q;

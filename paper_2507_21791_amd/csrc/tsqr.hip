@@ -400,6 +400,7 @@ void tsqr_down(const TsqrPlan& tp, double* ws, hipStream_t st) {
                        dim3(kThreads), 0, st, ws + tp.q_off[l],
                        ws + tp.c_off[l], tp.nodes[l - 1], fan, s,
                        ws + tp.c_off[l - 1], l == tp.levels ? 1 : 0);
+    prof_name("tsqr_down_kernel");
     prof_end();
   }
 }
@@ -417,6 +418,7 @@ static hipError_t launch_tsqr_s(const TsqrPlan& tp, const T* v, int64_t ldv,
   prof_begin(BCGS_KERNEL_TSQR_LEAF, 0, esz * m * s, 2.0 * m * ss);
   hipLaunchKernelGGL((tq::leaf_kernel<T, S>), dim3((unsigned)tp.nchunks),
                      dim3(kThreads), lds, st, v, ldv, m, s, ws + tp.r_off[0]);
+  prof_name("tsqr_leaf_kernel<%s, %d>", type_name<T>(), S);
   prof_end();
   for (int l = 1; l <= tp.levels; ++l) {
     const double rows = (double)tp.nodes[l - 1] * s;
@@ -427,6 +429,7 @@ static hipError_t launch_tsqr_s(const TsqrPlan& tp, const T* v, int64_t ldv,
                        tp.nodes[l - 1], fan, s, ws + tp.r_off[l],
                        ws + tp.q_off[l], l == tp.levels ? 1 : 0, r_out, r_rs,
                        r_cs, syncs);
+    prof_name("tsqr_node_kernel<%d>", S);
     prof_end();
   }
   tsqr_down(tp, ws, st);
@@ -434,6 +437,7 @@ static hipError_t launch_tsqr_s(const TsqrPlan& tp, const T* v, int64_t ldv,
   hipLaunchKernelGGL((tq::apply_kernel<T, S>), dim3((unsigned)tp.nchunks),
                      dim3(kThreads), lds, st, v, ldv, m, s,
                      ws + tp.c_off[0], dst, ldd);
+  prof_name("tsqr_apply_kernel<%s, %d>", type_name<T>(), S);
   prof_end();
   return hipGetLastError();
 }

@@ -382,6 +382,7 @@ static hipError_t launch_wave_tsqr_s(const TsqrPlan& tp, const T* v,
   prof_begin(BCGS_KERNEL_TSQR_LEAF, 0, esz * m * S, 2.0 * m * ss);
   hipLaunchKernelGGL((tw::leaf_kernel<T, S>), wgs(tp.nchunks), dim3(256), 0,
                      st, v, ldv, m, tp.nchunks, ws + tp.r_off[0]);
+  prof_name("tsqr_wave_leaf_kernel<%s, %d>", type_name<T>(), S);
   prof_end();
   for (int l = 1; l <= tp.levels; ++l) {
     const double rows = (double)tp.nodes[l - 1] * S;
@@ -390,12 +391,14 @@ static hipError_t launch_wave_tsqr_s(const TsqrPlan& tp, const T* v,
                        ws + tp.r_off[l - 1], tp.nodes[l - 1], fan,
                        tp.nodes[l], ws + tp.r_off[l], ws + tp.q_off[l],
                        l == tp.levels ? 1 : 0, r_out, r_rs, r_cs, syncs);
+    prof_name("tsqr_wave_node_kernel<%d>", S);
     prof_end();
   }
   tsqr_down(tp, ws, st);
   prof_begin(BCGS_KERNEL_TSQR_APPLY, 0, 2.0 * esz * m * S, 2.0 * m * ss);
   hipLaunchKernelGGL((tw::apply_kernel<T, S>), wgs(tp.nchunks), dim3(256), 0,
                      st, v, ldv, m, tp.nchunks, ws + tp.c_off[0], dst, ldd);
+  prof_name("tsqr_wave_apply_kernel<%s, %d>", type_name<T>(), S);
   prof_end();
   return hipGetLastError();
 }

@@ -223,7 +223,8 @@ def test_queue_null_handles_rejected():
     p = _problem()
     t = ctypes.c_uint64()
     out = bcgs.RequestStats()
-    assert L.bcgs_queue_submit(None, ctypes.byref(p), ctypes.byref(t)) == \
+    assert L.bcgs_queue_submit(None, ctypes.byref(p), None,
+                               ctypes.byref(t)) == \
         bcgs.BCGS_ERR_ARG
     assert L.bcgs_queue_poll(None, 1, ctypes.byref(out)) == bcgs.BCGS_ERR_ARG
     assert L.bcgs_queue_wait(None, 1, ctypes.byref(out)) == bcgs.BCGS_ERR_ARG

@@ -296,3 +296,33 @@ def test_queue_retries_breakdown_with_stable_variant():
     assert np.array_equal(host(r["Q"]), Qa)
     assert np.array_equal(Qq, Qa)
     compare(X, 16, "p-2s", host(r["Q"]), host(r["R"]), r["info"], kappa=1e12)
+
+
+def test_queue_orders_after_async_write_of_x():
+    """X written asynchronously on the caller's stream (a large device copy
+    from a second buffer and a scaling kernel, no synchronization) and
+    submitted straight away: every request reads the finished X, so its
+    result equals the one computed on X after a synchronization."""
+    import torch
+    from paper_2507_21791_amd import bcgs
+    log("[gpu] queue: submit right after an asynchronous write of X")
+    m, n, s = 200000, 128, 16
+    src = to_device(W.conditioned_host(m, n, 3, seed=91), torch.float64)
+    q = bcgs.Queue(hbm_budget_bytes=8 << 30, max_inflight=4)
+    outs = []
+    try:
+        for k in range(4):
+            X = bcgs.empty_fortran(m, n, torch.float64, "cuda")
+            X.fill_(float("nan"))          # what a too-early read would see
+            X.copy_(src)                   # enqueued, not waited for
+            X.mul_(2.0 ** k)               # exact scaling, still pending
+            t = q.submit(X, s, "p-1s")
+            outs.append((k, X, q.wait(t)))
+    finally:
+        q.close()
+    torch.cuda.synchronize()
+    for k, X, r in outs:
+        assert r["status"] == 0, r
+        Qa, Ra, ws = bcgs.qr(X, s, "p-1s")
+        torch.cuda.synchronize()
+        assert torch.equal(r["Q"], Qa) and torch.equal(r["R"], Ra), k

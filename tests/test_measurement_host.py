@@ -1,7 +1,6 @@
-"""Host logic of the measurement: kernel names decoded from launch tags
-(they must match the names rocprofv3 reports, which the traffic lookup
-keys on) and the profile summaries' byte models, on synthetic counter
-files.  No GPU."""
+"""Host logic of the measurement: the profile summaries' byte models on
+synthetic counter files, and the kernel names of the built library.  No
+GPU."""
 
 import csv
 import os
@@ -11,36 +10,7 @@ import pytest
 import bench
 from paper_2507_21791_amd import prof_summary as P
 
-
-def _tag(nw, pc, nbuf, scr2, tr, maxp, ntb, f32=False, reg=False):
-    # the launcher's encoding 1 W P B S TT PP N
-    return (1000000000 + nw * 100000000 + (pc + (4 if f32 else 0)) * 10000000
-            + (nbuf + (5 if reg else 0)) * 1000000 + (100000 if scr2 else 0)
-            + (tr % 100) * 1000 + maxp * 10 + ntb)
-
-
-@pytest.mark.parametrize("args,name", [
-    ((4, 2, 2, 0, 16, 7, 2), "pass16_kernel<double, 16, 2, 272, 7, true, 2, false>"),
-    ((4, 2, 2, 1, 16, 7, 2), "pass16_s2_kernel<double, 16, 2, 256, 7, true, 2, false>"),
-    ((4, 2, 2, 1, 16, 5, 1), "pass16_s2_kernel<double, 16, 2, 256, 5, true, 1, false>"),
-    ((4, 2, 2, 0, 32, 5, 2), "pass16_kernel<double, 32, 2, 128, 5, true, 2, false>"),
-    ((4, 2, 2, 0, 64, 2, 0), "pass16_kernel<double, 64, 2, 64, 2, false, 1, false>"),
-    ((8, 1, 2, 0, 32, 2, 1),
-     "pass16_deep_kernel<double, 32, 2, 272, 8, false, 2, true, 1, false>"),
-    ((4, 1, 4, 1, 16, 9, 2),
-     "pass16_deep_kernel<double, 16, 4, 272, 4, true, 9, true, 2, false>"),
-])
-def test_pass_kernel_names_from_tags(args, name):
-    assert bench.kernel_name("pass", _tag(*args)) == name
-
-
-def test_register_staged_and_binary32_names():
-    t = _tag(4, 2, 2, 1, 16, 7, 2, reg=True)
-    assert bench.kernel_name("pass", t) == (
-        "pass16_s2_kernel<double, 16, 2, 256, 7, true, 2, true>")
-    t = _tag(4, 2, 2, 0, 32, 5, 1, f32=True)
-    assert bench.kernel_name("pass", t) == (
-        "pass16_kernel<float, 32, 2, 272, 5, true, 1, false>")
+from kernel_names import library_kernel_names
 
 
 def _write_counters(d, rows):
@@ -109,3 +79,15 @@ def test_request_counts_to_bytes(tmp_path):
     assert float(f[-4]) == pytest.approx(1.44, abs=1e-4)
     assert float(f[-3]) == pytest.approx(0.80, abs=1e-4)
     assert float(f[-1]) == pytest.approx(10 / 13, abs=1e-3)
+
+
+def test_library_kernels_have_short_names():
+    """Every kernel of the built library maps to a short name of the form
+    the profile summaries and the bench's launch records use."""
+    names = library_kernel_names()
+    assert any(n.startswith("pass16_s2_kernel<double, 16, 2, 256,")
+               for n in names), sorted(names)[:20]
+    assert "gram_reduce_kernel" in names
+    assert "epilogue_kernel<16>" in names
+    assert "tsqr_wave_apply_kernel<double, 16>" in names
+    assert all("(" not in n and "::" not in n for n in names)
