@@ -545,6 +545,8 @@ def main():
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-small", action="store_true")
+    ap.add_argument("--ld-pad", type=int, default=16,
+                    help="leading dimension of X and Q = m + LD_PAD")
     ap.add_argument("--no-twin", action="store_true")
     ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--sweep-steps", type=int, default=3)
@@ -574,8 +576,14 @@ def main():
     m, n, s = w["m"], w["n"], w["s"]
     log(f"[bench] generating {args.workload} X: m={m} n={n} s={s}")
     X = W.make_device(args.workload, m=m)
+    ld = m + args.ld_pad
+    if args.ld_pad:
+        Xp = bcgs.empty_fortran(m, n, torch.float64, "cuda", ld=ld)
+        Xp.copy_(X)
+        del X
+        X = Xp
     torch.cuda.synchronize()
-    Q = bcgs.empty_fortran(m, n, torch.float64, "cuda")
+    Q = bcgs.empty_fortran(m, n, torch.float64, "cuda", ld=ld)
     R = bcgs.empty_fortran(n, n, torch.float64, "cuda")
 
     if args.copy_calibration:
@@ -633,8 +641,10 @@ def main():
         "data": "synthetic",
         "config": {"workload": (f"{args.workload}: m={m} n={n} s={s} "
                                 f"kappa=1e{w['decades']} FP64, variant "
-                                f"{variants[0]}"),
-                   "m": m, "n": n, "s": s, "variant": variants[0]},
+                                f"{variants[0]}, X and Q column-major "
+                                f"with leading dimension {ld}"),
+                   "m": m, "n": n, "s": s, "variant": variants[0],
+                   "ld": ld},
         "hbm_frac": round(head["gbs"] / HBM_PEAK_GBS, 4),
         "fp64_frac": round(head["tflops"] / FP64_PEAK_TFS, 4),
         "roofline": roofline(dom),

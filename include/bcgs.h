@@ -204,7 +204,12 @@ typedef struct {
  * runtime failure, BCGS_OK otherwise (count == 0 enqueues nothing).
  * Environment BCGS_BATCH_MODE=streams enqueues the same branches directly,
  * without the graph (for comparison); BCGS_BATCH_BRANCHES (1..16, default
- * 8) sets the number of branch streams. */
+ * 8) sets the number of branch streams.  BCGS_BATCH_MODE=persistent runs
+ * the whole batch as one persistent kernel whose workgroups claim
+ * (problem, step, row range) work items, with per-problem device-side
+ * barriers between dependent steps (same bits as the lone runs); it
+ * supports binary64 problems with s in {4, 8, 16} and returns
+ * BCGS_ERR_UNSUPPORTED (nothing enqueued) for any other batch. */
 bcgs_status bcgs_qr_batched(const bcgs_problem* probs, int32_t count,
                             hipStream_t stream);
 
@@ -244,15 +249,22 @@ void bcgs_tuning_clear(void);
 
 /* ---- request queue with continuous batching -------------------------------
  * For serving: callers on any thread submit requests without blocking; one
- * scheduler thread per queue admits them in arrival order onto up to
- * max_inflight library streams whenever a stream is free and the request's
- * HBM footprint (X + Q + R + its workspace) fits in the budget left by the
- * running requests (a request is always admitted when nothing runs, so one
- * larger than the budget still completes).  Requests admitted while others
+ * scheduler thread per queue admits them onto up to max_inflight library
+ * streams whenever a stream is free and the next request's HBM footprint
+ * (X + Q + R + its workspace) fits in the budget left by the running
+ * requests (a request is always admitted when nothing runs, so one larger
+ * than the budget still completes).  The next request is the oldest
+ * (BCGS_ADMIT_ARRIVAL) or the one whose estimated device time minus the
+ * time it has waited is least (BCGS_ADMIT_SHORTEST: the estimate is the
+ * streamed bytes at 3 TB/s plus 25 us per synchronization point, so small
+ * requests pass large ones, and a large one is passed for at most about
+ * its own estimate); a retry always goes first.  Requests admitted while others
  * run overlap with them on the device.  Each request runs exactly the
  * computation bcgs_qr_ex would run for it (same kernels, same tuned
  * choices), so its results are bitwise the same alone and in the mix. */
 typedef struct bcgs_queue* bcgs_queue_t;
+
+typedef enum { BCGS_ADMIT_ARRIVAL = 0, BCGS_ADMIT_SHORTEST = 1 } bcgs_admission;
 
 typedef struct {
     size_t hbm_budget_bytes;    /* > 0 */
@@ -264,6 +276,8 @@ typedef struct {
                                    once more, first in line, with
                                    retry_variant (same outputs) */
     int32_t retry_variant;      /* bcgs_variant, e.g. BCGS_P_2S */
+    int32_t admission;          /* bcgs_admission */
+    int32_t reserved;           /* 0 */
 } bcgs_queue_config;
 
 /* Outcome of one request; times are seconds on the host's steady clock
@@ -329,6 +343,34 @@ bcgs_status bcgs_queue_free_output(bcgs_queue_t q, void* ptr,
  * free the queue and its arena.  No other call on the queue may be in
  * progress or follow. */
 bcgs_status bcgs_queue_destroy(bcgs_queue_t q);
+
+/* ---- accuracy check ------------------------------------------------------
+ * The loss of orthogonality ||Q^T Q - I||_2 and the relative residual
+ * ||X - Q R||_2 / ||X||_2 of a computed factorization (section 1's two
+ * accuracy measures) are 2-norms of n x n symmetric matrices built from
+ * three Gram matrices.  bcgs_check forms them on the device:
+ *   GQ = Q^T Q,  GE = E^T E with E = X - Q R,  GX = X^T X
+ * each summed over chunks of 4096 rows with a compensated (two-sum)
+ * addition of the chunk products, so the check's own error does not grow
+ * with m; the caller takes the largest absolute eigenvalues (of GQ - I, GE,
+ * GX) on the host.  Only the upper triangle of R is read.
+ *   X, Q      m x n, binary64 (BCGS_FP64) or binary32 (BCGS_FP32_BULK, read
+ *             and widened to binary64), ldx, ldq >= m
+ *   R         n x n binary64, ldr >= n
+ *   GQ, GE, GX  n x n binary64 outputs, both triangles, ldg >= n
+ *   workspace device buffer of bcgs_check_workspace_size(m, n) bytes,
+ *             256-byte aligned, used until the stream reaches its end
+ * Everything is enqueued on `stream`; nothing is allocated.  BCGS_ERR_ARG
+ * (nothing enqueued) for NULL pointers, m < n, n < 1, short leading
+ * dimensions or a small/misaligned workspace; BCGS_ERR_HIP if a launch
+ * fails. */
+size_t bcgs_check_workspace_size(int64_t m, int64_t n);
+
+bcgs_status bcgs_check(const void* X, int64_t ldx, const void* Q,
+                       int64_t ldq, const double* R, int64_t ldr, int64_t m,
+                       int64_t n, bcgs_precision precision, double* GQ,
+                       double* GE, double* GX, int64_t ldg, void* workspace,
+                       size_t ws_bytes, hipStream_t stream);
 
 /* ---- launch profiling ----------------------------------------------------
  * Between bcgs_profile_start(stream) and bcgs_profile_stop(stream, ...), every

@@ -67,7 +67,11 @@ class QueueConfig(ctypes.Structure):
                 ("max_inflight", ctypes.c_int32), ("device", ctypes.c_int32),
                 ("output_arena_bytes", ctypes.c_size_t),
                 ("retry_on_breakdown", ctypes.c_int32),
-                ("retry_variant", ctypes.c_int32)]
+                ("retry_variant", ctypes.c_int32),
+                ("admission", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+ADMISSION = {"arrival": 0, "shortest": 1}
 
 
 class RequestStats(ctypes.Structure):
@@ -131,6 +135,16 @@ _PROTOS = {
     "bcgs_queue_free_output": (ctypes.c_int, [ctypes.c_void_p,
                                               ctypes.c_void_p,
                                               ctypes.c_void_p]),
+    "bcgs_check_workspace_size": (ctypes.c_size_t, [ctypes.c_int64,
+                                                    ctypes.c_int64]),
+    "bcgs_check": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64,
+                                  ctypes.c_void_p, ctypes.c_int64,
+                                  ctypes.c_void_p, ctypes.c_int64,
+                                  ctypes.c_int64, ctypes.c_int64,
+                                  ctypes.c_int, ctypes.c_void_p,
+                                  ctypes.c_void_p, ctypes.c_void_p,
+                                  ctypes.c_int64, ctypes.c_void_p,
+                                  ctypes.c_size_t, ctypes.c_void_p]),
     "bcgs_profile_start": (ctypes.c_int, [ctypes.c_void_p]),
     "bcgs_profile_stop": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p,
                                            ctypes.c_int32]),
@@ -183,9 +197,14 @@ def sync_count(m, n, s, variant):
     return lib().bcgs_sync_count(m, n, s, VARIANTS[variant])
 
 
-def empty_fortran(m, n, dtype, device):
+def empty_fortran(m, n, dtype, device, ld=None):
+    """Uninitialised m x n column-major tensor with leading dimension ld
+    (default m): strides (1, ld)."""
     import torch
-    return torch.empty((n, m), dtype=dtype, device=device).t()
+    ld = m if ld is None else ld
+    if ld < m:
+        raise ValueError(f"leading dimension {ld} < rows {m}")
+    return torch.empty((n, ld), dtype=dtype, device=device)[:, :m].t()
 
 
 class Workspace:
@@ -294,6 +313,62 @@ def get_info(stream=None):
     return info
 
 
+class Checker:
+    """bcgs_check with a reusable device workspace and Gram buffers.
+
+    ``grams`` enqueues the three n x n Gram matrices (Q^T Q, E^T E with
+    E = X - Q R, X^T X) on the stream and returns them as device tensors;
+    ``measures`` turns them into the loss of orthogonality and the relative
+    residual: largest absolute eigenvalues of the small symmetric matrices,
+    taken on the host."""
+
+    def __init__(self, device="cuda"):
+        self.device = device
+        self.ws = None
+        self.nbytes = 0
+        self.G = None
+
+    def grams(self, X, Q, R, precision="fp64", stream=None):
+        import torch
+        m, n = X.shape
+        need = lib().bcgs_check_workspace_size(m, n)
+        if need == 0:
+            raise BcgsError(BCGS_ERR_ARG, "bcgs_check_workspace_size")
+        if need > self.nbytes:
+            self.ws = torch.empty(need + 256, dtype=torch.uint8,
+                                  device=self.device)
+            self.nbytes = need
+        ptr = self.ws.data_ptr() + (-self.ws.data_ptr()) % 256
+        G = torch.empty((3, n, n), dtype=torch.float64, device=self.device)
+        st = lib().bcgs_check(
+            ctypes.c_void_p(X.data_ptr()), _col_major(X, "X"),
+            ctypes.c_void_p(Q.data_ptr()), _col_major(Q, "Q"),
+            ctypes.c_void_p(R.data_ptr()), _col_major(R, "R"), m, n,
+            PRECISIONS[precision], ctypes.c_void_p(G[0].data_ptr()),
+            ctypes.c_void_p(G[1].data_ptr()), ctypes.c_void_p(G[2].data_ptr()),
+            n, ctypes.c_void_p(ptr), self.nbytes, _stream_handle(stream))
+        if st != BCGS_OK:
+            raise BcgsError(st, "bcgs_check")
+        return G
+
+    @staticmethod
+    def measures(G):
+        import numpy as np
+        g = G.cpu().numpy()
+
+        def norm2(M):
+            M = 0.5 * (M + M.T)
+            return float(np.max(np.abs(np.linalg.eigvalsh(M))))
+        n = g.shape[1]
+        loo = norm2(g[0] - np.eye(n))
+        res = max(norm2(g[1]), 0.0) ** 0.5 / norm2(g[2]) ** 0.5
+        return loo, res
+
+    def __call__(self, X, Q, R, precision="fp64", stream=None):
+        """(loss of orthogonality, relative residual); synchronizes."""
+        return self.measures(self.grams(X, Q, R, precision, stream))
+
+
 class Batch:
     """A list of problems with device outputs and one info record each, in
     the layout bcgs_qr_batched takes.  Keeps the tensors alive."""
@@ -382,15 +457,18 @@ class Queue:
     tensors of every request until it is collected."""
 
     def __init__(self, hbm_budget_bytes, max_inflight=8, device=0,
-                 output_arena_bytes=0, retry_variant=None):
+                 output_arena_bytes=0, retry_variant=None,
+                 admission="arrival"):
         """retry_variant: variant name a request that breaks down is rerun
-        with once (e.g. "p-2s"), or None."""
+        with once (e.g. "p-2s"), or None.  admission: "arrival" (oldest
+        first) or "shortest" (least estimated work net of waiting time)."""
         self.handle = ctypes.c_void_p()
         cfg = QueueConfig(int(hbm_budget_bytes), int(max_inflight),
                           int(device), int(output_arena_bytes),
                           0 if retry_variant is None else 1,
                           0 if retry_variant is None
-                          else VARIANTS[retry_variant])
+                          else VARIANTS[retry_variant],
+                          ADMISSION[admission], 0)
         st = lib().bcgs_queue_create(ctypes.byref(cfg),
                                      ctypes.byref(self.handle))
         if st != BCGS_OK:

@@ -261,6 +261,14 @@ bcgs_status bcgs_qr_batched(const bcgs_problem* probs, int32_t count,
     memcpy(k, &b.arena, sizeof(void*));
   }
   const char* mode = getenv("BCGS_BATCH_MODE");
+  if (mode && strcmp(mode, "persistent") == 0) {
+    // one persistent launch when every problem's steps have a body there
+    bool used = false;
+    const bcgs_status r =
+        persist_run(plans, probs, offs, b.arena, key, stream, &used);
+    if (used || r != BCGS_OK) return r;
+    return BCGS_ERR_UNSUPPORTED;
+  }
   if (mode && strcmp(mode, "streams") == 0) {
     // same schedule on the branch streams without a graph (comparison)
     return enqueue_branches(b, plans, probs, offs, order, branch_of, stream);
@@ -374,6 +382,9 @@ bcgs_status bcgs_autotune(const bcgs_problem* probs, int32_t count,
     if (res == BCGS_OK && (p.precision == BCGS_FP64 && s <= 16)) {
       const Tuning base = best;
       for (int sh = 0; sh < pass16_shape_count(); ++sh) {
+        // small problems: four-wave shapes only (as the automatic choice)
+        if (p.m <= pass16_small_rows() && !pass16_shape_four_waves(sh))
+          continue;
         Tuning t = base;
         t.shape = sh;
         float ms;
@@ -440,6 +451,7 @@ void bcgs_tuning_clear(void) {
 namespace bcgs {
 
 void batch_release() {
+  persist_release();
   std::lock_guard<std::mutex> lock(g_batch_mu);
   for (auto& kv : g_batch) {
     BatchState& b = kv.second;

@@ -14,6 +14,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <vector>
+
 #include "bcgs.h"
 
 namespace bcgs {
@@ -133,6 +135,14 @@ bcgs_status check_problem(const void* X, int64_t ldx, int64_t m, int64_t n,
                           int64_t ldr, const bcgs_info* d_info, Plan* p);
 // Frees the batch arenas, cached graphs and library streams (batch.hip).
 void batch_release();
+// The batch as one persistent launch (batch_persist.hip); *used = false
+// when some problem needs a kernel the persistent launch does not run.
+bcgs_status persist_run(const std::vector<Plan>& plans,
+                        const bcgs_problem* probs,
+                        const std::vector<size_t>& offs, void* arena,
+                        const std::vector<char>& key, hipStream_t stream,
+                        bool* used);
+void persist_release();
 
 // Enqueue the whole factorization on `st` (workspace of p.bytes bytes).
 bcgs_status run_problem(const Plan& p, const void* X, int64_t ldx, void* Q,
@@ -153,6 +163,11 @@ hipError_t launch_pass16(const PassArgs<double>& a, int64_t m,
                          const Tuning& tune, hipStream_t st, int* tag,
                          int* G_out);
 int pass16_shape_count();
+// shape `shape` has four waves per workgroup (the batched persistent
+// kernel runs those); problems of at most pass16_small_rows() rows choose
+// only such shapes
+bool pass16_shape_four_waves(int shape);
+int64_t pass16_small_rows();
 // The same pass on binary32 storage (FP32-bulk form).
 hipError_t launch_pass16_f32(const PassArgs<float>& a, int64_t m,
                              const Tuning& tune, hipStream_t st, int* tag,
@@ -208,6 +223,31 @@ struct EpiArgs {
   double* r; int64_t ldr;
   bcgs_info* info;
 };
+
+// Recording of a schedule for the batched persistent kernel
+// (batch_persist.hip): while the calling thread records, every launcher
+// describes its launch as a step of work items instead of launching it
+// (and returns hipSuccess); a launch the persistent kernel cannot run marks
+// the recording unsupported.
+bool rec_active();
+void rec_unsupported();
+void rec_reduce(const double* partial, int G, int64_t elems, double* out,
+                int32_t* syncs, int64_t blocks);
+void rec_fill(double* p, int64_t rows, int64_t cols, int64_t ld, double v,
+              int64_t blocks);
+void rec_init(bcgs_info* info);
+void rec_epi(const EpiArgs& a);
+void rec_tsqr_leaf(int S, const double* v, int64_t ldv, int64_t m,
+                   int64_t nchunks, double* rleaf, int64_t blocks);
+void rec_tsqr_node(int S, const double* rprev, int64_t nprev, int fan,
+                   int64_t nnodes, double* rcur, double* qcur, int is_root,
+                   double* r_out, int64_t r_rs, int64_t r_cs, int32_t* syncs,
+                   int64_t blocks);
+void rec_tsqr_down(const double* qpar, const double* cpar, int64_t nchild,
+                   int fan, int s, double* cchild, int parent_is_root);
+void rec_tsqr_apply(int S, const double* v, int64_t ldv, int64_t m,
+                    int64_t nchunks, const double* cleaf, double* dst,
+                    int64_t ldd, int64_t blocks);
 
 // launch profiling (profile.hip); no-ops unless bcgs_profile_start ran on
 // the stream being attached

@@ -28,6 +28,7 @@
 #include <mutex>
 
 #include "common.h"
+#include "small_impl.h"
 
 namespace bcgs {
 
@@ -95,17 +96,7 @@ void prof_retag(int tag);
 
 // syncs starts at zero; every reduction and every TSQR root adds one as it
 // completes, so the record reports the synchronization points that ran
-__global__ void info_init_kernel(bcgs_info* info) {
-  if (threadIdx.x == 0) {
-    info->status = BCGS_OK;
-    info->block = -1;
-    info->pivot = -1;
-    info->stage = -1;
-    info->syncs = 0;
-    info->reserved = 0;
-    info->value = 0.0;
-  }
-}
+__global__ void info_init_kernel(bcgs_info* info) { info_init_body(info); }
 
 // ------------------------------------------------------------ schedule ---
 template <typename T>
@@ -263,8 +254,12 @@ struct Run {
   void run_steps() {
     const int s = p.s, q = p.q, sp = p.sp;
     check(launch_fill(R, p.n, p.n, ldr, 0.0, st));
-    hipLaunchKernelGGL(info_init_kernel, dim3(1), dim3(64), 0, st, info);
-    check(hipGetLastError());
+    if (rec_active()) {
+      rec_init(info);
+    } else {
+      hipLaunchKernelGGL(info_init_kernel, dim3(1), dim3(64), 0, st, info);
+      check(hipGetLastError());
+    }
     // [Q_0, R_00] = TSQR(X_0)
     tsqr(xb(0), ldx, qb(0), R, 1, ldr);
     if (q == 1) return;

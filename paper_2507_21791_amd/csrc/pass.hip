@@ -27,6 +27,7 @@
 //   FP64 (v_mfma_f64_16x16x4f64): l / 16 + 4 v
 //   FP32 (v_mfma_f32_16x16x4f32): 4 (l / 16) + v
 #include "common.h"
+#include "small_impl.h"
 
 namespace bcgs {
 
@@ -255,47 +256,20 @@ __global__ __launch_bounds__(kThreads) void pass_kernel(PassArgs<T> a) {
   }
 }
 
-// Fixed-order sum of the per-workgroup partial Gram matrices:
-// out[e] = sum_g partial[g][e], four interleaved partial sums per entry
-// combined in a fixed order.
-// Sum of the G per-workgroup partials, entry by entry, in a fixed order:
-// wave w of 16 adds partials w, w+16, ... into four interleaved running sums
-// (so four loads are in flight), and the 16 wave sums are added in wave
-// order.  The result depends only on G, never on timing.
-constexpr int kRedWaves = 16;
-
 __global__ __launch_bounds__(kRedWaves * 64) void gram_reduce_kernel(
     const double* __restrict__ partial, int G, int64_t elems,
     double* __restrict__ out, int32_t* syncs) {
-  __shared__ double red[kRedWaves][64];
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int64_t e = (int64_t)blockIdx.x * 64 + lane;
-  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-  if (e < elems) {
-    int g = w;
-    for (; g + 3 * kRedWaves < G; g += 4 * kRedWaves) {
-      a0 += partial[(size_t)g * elems + e];
-      a1 += partial[(size_t)(g + kRedWaves) * elems + e];
-      a2 += partial[(size_t)(g + 2 * kRedWaves) * elems + e];
-      a3 += partial[(size_t)(g + 3 * kRedWaves) * elems + e];
-    }
-    for (; g < G; g += kRedWaves) a0 += partial[(size_t)g * elems + e];
-  }
-  red[w][lane] = (a0 + a1) + (a2 + a3);
-  __syncthreads();
-  if (w == 0 && e < elems) {
-    double t = red[0][lane];
-#pragma unroll
-    for (int i = 1; i < kRedWaves; ++i) t += red[i][lane];
-    out[e] = t;
-  }
-  // one synchronization point completed (counted by one thread)
-  if (syncs != nullptr && blockIdx.x == 0 && tid == 0) *syncs += 1;
+  __shared__ double red[kRedWaves * 64];
+  reduce_body(partial, G, elems, out, syncs, red, blockIdx.x);
 }
 
 hipError_t launch_gram_reduce(const double* partial, int G, int64_t elems,
                               double* out, int32_t* syncs, hipStream_t st) {
   const int64_t blocks = cdiv(elems, 64);
+  if (rec_active()) {
+    rec_reduce(partial, G, elems, out, syncs, blocks);
+    return hipSuccess;
+  }
   prof_begin(BCGS_KERNEL_REDUCE, 0, 8.0 * elems * (G + 1),
              (double)elems * G);
   hipLaunchKernelGGL(gram_reduce_kernel, dim3((unsigned)blocks),
@@ -320,6 +294,10 @@ template <typename T, bool GRAM, int NTB, int MAXA>
 static hipError_t launch_one(const PassArgs<T>& a, int G, hipStream_t st,
                              int* tag) {
   *tag = (sizeof(T) == 4 ? 1000 : 0) + (GRAM ? 100 : 0) + 10 * NTB + MAXA;
+  if (rec_active()) {
+    rec_unsupported();
+    return hipSuccess;
+  }
   auto kern = pass_kernel<T, GRAM, NTB, MAXA>;
   const size_t lds = pass_lds_bytes(a);
   static bool attr_done = false;

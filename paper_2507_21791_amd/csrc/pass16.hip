@@ -52,6 +52,12 @@ size_t pass16_lds_bytes(int ncols_p, int tr, int nw) {
 
 int pass16_shape_count() { return p16::kNShapes; }
 
+bool pass16_shape_four_waves(int shape) {
+  return shape >= 0 && shape < p16::kNShapes && p16::kShapes[shape].nw == 4;
+}
+
+int64_t pass16_small_rows() { return p16::kSmallRows; }
+
 // Returns hipErrorNotSupported (without launching) when this kernel cannot
 // take the pass.  *G_out receives the number of workgroups used (the row
 // split is a function of m and of the chosen shape only).

@@ -548,11 +548,23 @@ struct Kernel {
       b3 = b3s;
     }
     __shared__ T scr[(SCR2 ? 2 : 1) * KG * TR * kScrRow<T>];
+    run_with(a, b0, b1, b2, b3, scr, blockIdx.x, gridDim.x);
+  }
+
+  // Elements of LDS the shape needs: NBUF tile buffers of TE, and the
+  // partial-sum area
+  static constexpr int kScrElems = (SCR2 ? 2 : 1) * KG * TR * kScrRow<T>;
+
+  // The pass as workgroup g of G on the given LDS buffers (b2, b3 used only
+  // with NBUF > 2, 3): the body of the pass kernels, and of the batched
+  // persistent kernel, which hands it its work items.
+  static __device__ __forceinline__ void run_with(const Args& a, T* b0, T* b1,
+                                                  T* b2, T* b3, T* scr,
+                                                  int64_t g, int64_t G) {
     T* const bufs[4] = {b0, b1, b2, b3};
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform
     const int li = lane & 15, lk = lane >> 4;
-    const int64_t g = blockIdx.x;
     // Tiles of this workgroup: nfull full tiles at rows row_begin + t ts,
     // then possibly one short tile of rows [rt, rt_end).  Contiguous: a
     // range of rows_per_wg rows per workgroup.  Interleaved: full tile i of
@@ -561,7 +573,7 @@ struct Kernel {
     // every column.
     int64_t row_begin, ts, nfull, rt, rt_end;
     if (a.interleave) {
-      const int64_t G = gridDim.x, nt = a.m / TR;
+      const int64_t nt = a.m / TR;
       row_begin = g * TR;
       ts = G * TR;
       nfull = nt > g ? (nt - g + G - 1) / G : 0;
@@ -732,6 +744,10 @@ void pass16_deep_kernel(ArgsT<T> a) {
   Kernel<T, TR, NBUF, CAP, 1, NW, SCR2, MAXP, GRAM, NTB, REG, 0>::run(a);
 }
 
+// recording of a pass (batch_persist.hip): tile rows, waves, B blocks of
+// the Gram (0: none), workgroups
+void rec_pass16(const ArgsT<double>& a, int tr, int nw, int gram_ntb, int G);
+
 template <typename T, int TR, int NBUF, int CAP, int PC, int NW, bool SCR2,
           int MAXP, bool GRAM, int NTB, bool REG, int KS = 0>
 static hipError_t go(const ArgsT<T>& a, int G, hipStream_t st, int* tag) {
@@ -743,6 +759,15 @@ static hipError_t go(const ArgsT<T>& a, int G, hipStream_t st, int* tag) {
          (PC + (sizeof(T) == 4 ? 4 : 0)) * 10000000 +
          (NBUF + (REG ? 5 : 0)) * 1000000 + (SCR2 ? 100000 : 0) +
          (TR % 100) * 1000 + (MAXP + (KS ? 50 : 0)) * 10 + (GRAM ? NTB : 0);
+  if (rec_active()) {
+    // the same pass as a step of G work items: any shape with four waves
+    // per workgroup (K split four ways, as here) gives the same bits
+    if constexpr (sizeof(T) == 8 && NW == 4)
+      rec_pass16(a, TR, NW, GRAM ? NTB : 0, G);
+    else
+      rec_unsupported();
+    return hipSuccess;
+  }
   if constexpr (PC == 2) {
     if constexpr (SCR2)
       hipLaunchKernelGGL(
@@ -769,6 +794,10 @@ static hipError_t go(const ArgsT<T>& a, int G, hipStream_t st, int* tag) {
 // (tile rows, buffers, column capacity, workgroups per CU, waves, both
 // partial-sum areas)
 struct Shape { int tr, nbuf, cap, per_cu, nw, scr2; };
+
+// problems of at most this many rows take shapes of four waves when one
+// fits (see launch_pass16_t)
+constexpr int64_t kSmallRows = int64_t(1) << 18;
 
 // Binary64 shapes.  The launcher picks among these (or takes the tuned /
 // BCGS_PASS16_SHAPE index); dispatch() instantiates the same list, entry by
@@ -949,13 +978,19 @@ hipError_t launch_pass16_t(const PassArgs<T>& pa, int64_t m,
     // by the stream and take the 32-row, 8-wave shape.
     static const int kHeavy[] = {0, 3, 7, 4, 2, 5, 1, 6};
     static const int kLight[] = {0, 3, 2, 4, 7, 5, 1, 6};
+    // small problems (the sizes batches and queues mix) keep to shapes of
+    // four waves, which the batched persistent kernel also runs, so a
+    // problem gives the same bits alone and in a batch
+    static const int kSmall[] = {0, 3, 7, 4, 5, 2, 1, 6};
     static_assert(sizeof(kHeavy) / sizeof(int) == nshapes, "every shape");
-    const int* order = (pa.gram && ntb == 2) ? kHeavy : kLight;
+    const bool small = m <= kSmallRows;
+    const int* order = small ? kSmall
+                             : (pa.gram && ntb == 2) ? kHeavy : kLight;
     // Measured per pass (tall PIPI+, P-1S): a pass with one Gram B block and
     // a block update runs faster in shape 7 than in the 8-wave 32-row shape
     // from 129 up to 208 columns (256 with both updates); wider, or with the
     // Gram or an update alone (BCGSI+), the 32-row shape is faster.
-    if (pick < 0 && pa.gram && ntb == 1 && (pa.upd1 || pa.upd2) &&
+    if (pick < 0 && !small && pa.gram && ntb == 1 && (pa.upd1 || pa.upd2) &&
         pa.ncols_p > 128 && pa.ncols_p <= (pa.upd1 && pa.upd2 ? 256 : 208) &&
         shape_fits<T>(shapes[7], pa.ncols_p, shared, npairs, reg))
       pick = 7;

@@ -3,9 +3,14 @@
 // Callers submit factorization requests (bcgs_problem: device X, Q, R and
 // info) from any thread; submit never blocks on the device.  One scheduler
 // thread per queue owns a fixed set of device streams ("slots", at most
-// max_inflight) and, in arrival order, admits the oldest waiting request as
-// soon as a slot is free and the request's HBM footprint (X + Q + R + its
-// workspace) fits in what the running requests leave of the budget.  An
+// max_inflight) and admits a waiting request as soon as a slot is free and
+// the request's HBM footprint (X + Q + R + its workspace) fits in what the
+// running requests leave of the budget.  Which request: the oldest
+// (arrival order), or the one with the least estimated work net of its
+// waiting time (shortest first with aging: the estimate, in seconds, is
+// the streamed bytes over 3 TB/s plus 25 us per synchronization point, and
+// every second spent waiting takes one second off it, so a large request
+// waits at most about its own estimate for smaller ones).  An
 // admitted request runs its whole schedule on its slot's stream, exactly as
 // bcgs_qr_ex would (same kernels, same tuned choices, same bits), so
 // requests that arrive while others run overlap with them on the device.
@@ -54,6 +59,8 @@ struct Request {
   bool own = false;        // Q and R allocated by the queue at admission
   bool placed = false;     // queue-allocated outputs already assigned
   bool done = false;
+  bool first = false;      // a retry: admitted before everything else
+  double est = 0;          // estimated device seconds (admission order)
   hipEvent_t ready = nullptr;  // recorded on the submitter's stream
   bcgs_request_stats stats{};
 };
@@ -136,6 +143,7 @@ struct bcgs_queue {
   size_t in_use = 0;
   int retry = 0;                     // rerun breakdowns with retry_variant
   int retry_variant = 0;
+  int admission = BCGS_ADMIT_ARRIVAL;
   std::chrono::steady_clock::time_point t0;
   std::mutex mu;
   std::condition_variable cv_work;   // scheduler: new request / stop
@@ -153,6 +161,7 @@ struct bcgs_queue {
                                          t0).count();
   }
   void run();
+  std::deque<uint64_t>::iterator pick();
 };
 
 namespace bcgs {
@@ -169,6 +178,20 @@ size_t footprint_of(const bcgs_problem& p, const Plan& plan) {
   const size_t q = (size_t)((p.n - 1) * p.ldq + p.m) * esz;
   const size_t r = (size_t)((p.n - 1) * p.ldr + p.n) * 8;
   return x + q + r + plan.bytes;
+}
+
+// Estimated device time of a request in seconds, for the shortest-first
+// admission order only: P-1S-like schedules read Q_{1:k} once per block
+// column (n q / 2 columns over the run), BCGSI+ twice; plus X, U and Q
+// once each, and a fixed cost per synchronization point.
+double estimate_seconds(const bcgs_problem& p) {
+  const double esz = p.precision == BCGS_FP32_BULK ? 4.0 : 8.0;
+  const double q = (double)(p.n / p.s);
+  const double reads = p.variant == BCGS_I_PLUS ? 2.0 : 1.0;
+  const double cols = reads * (double)p.n * q / 2.0 + 3.0 * (double)p.n;
+  const double syncs =
+      (double)bcgs_sync_count(p.m, p.n, p.s, (bcgs_variant)p.variant);
+  return (double)p.m * esz * cols / 3e12 + 25e-6 * syncs;
 }
 
 // Start request `t` on slot `sl` (scheduler thread, lock not held).
@@ -242,6 +265,7 @@ void bcgs_queue::run() {
         rq.footprint = footprint_of(rq.prob, again);
         rq.stats.variant = retry_variant;
         rq.stats.status = BCGS_PENDING;
+        rq.first = true;
         waiting.push_front(tk);
         continue;
       }
@@ -261,7 +285,8 @@ void bcgs_queue::run() {
     }
     bool blocked = false;
     while (!waiting.empty() && running < nslots) {
-      Request& rq = reqs[waiting.front()];
+      const auto at = pick();
+      Request& rq = reqs[*at];
       if (running > 0 && in_use + rq.footprint > budget) break;
       if (rq.own && !rq.placed) {
         // outputs from the arena: Q then R, both or neither
@@ -274,7 +299,7 @@ void bcgs_queue::run() {
             break;
           }
           // being destroyed and nothing can free space: give up on it
-          waiting.pop_front();
+          waiting.erase(at);
           rq.stats.status = BCGS_ERR_NOMEM;
           rq.stats.t_start = rq.stats.t_done = now();
           rq.done = true;
@@ -290,8 +315,8 @@ void bcgs_queue::run() {
       ++rq.stats.attempts;
       int k = 0;
       while (slots[k].ticket) ++k;
-      const uint64_t t = waiting.front();
-      waiting.pop_front();
+      const uint64_t t = *at;
+      waiting.erase(at);
       in_use += rq.footprint;
       ++running;
       slots[k].ticket = t;
@@ -334,6 +359,24 @@ void bcgs_queue::run() {
   }
 }
 
+// The waiting request to admit next (lock held, waiting not empty).
+std::deque<uint64_t>::iterator bcgs_queue::pick() {
+  if (admission == BCGS_ADMIT_ARRIVAL) return waiting.begin();
+  const double t = now();
+  auto best = waiting.begin();
+  double key_best = 0;
+  for (auto it = waiting.begin(); it != waiting.end(); ++it) {
+    const Request& rq = reqs[*it];
+    if (rq.first) return it;
+    const double key = rq.est - (t - rq.stats.t_submit);
+    if (it == waiting.begin() || key < key_best) {
+      best = it;
+      key_best = key;
+    }
+  }
+  return best;
+}
+
 extern "C" {
 
 bcgs_status bcgs_queue_create(const bcgs_queue_config* cfg,
@@ -345,6 +388,9 @@ bcgs_status bcgs_queue_create(const bcgs_queue_config* cfg,
   if (cfg->retry_on_breakdown &&
       (cfg->retry_variant < BCGS_I_PLUS || cfg->retry_variant > BCGS_I_PLUS_1S))
     return BCGS_ERR_ARG;
+  if (cfg->admission != BCGS_ADMIT_ARRIVAL &&
+      cfg->admission != BCGS_ADMIT_SHORTEST)
+    return BCGS_ERR_ARG;
   const size_t arena = cfg->output_arena_bytes & ~size_t(255);
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess) return BCGS_ERR_HIP;
@@ -355,6 +401,7 @@ bcgs_status bcgs_queue_create(const bcgs_queue_config* cfg,
   q->nslots = cfg->max_inflight;
   q->retry = cfg->retry_on_breakdown != 0;
   q->retry_variant = cfg->retry_variant;
+  q->admission = cfg->admission;
   q->t0 = std::chrono::steady_clock::now();
   int prev = 0;
   (void)hipGetDevice(&prev);
@@ -422,6 +469,7 @@ bcgs_status bcgs_queue_submit(bcgs_queue_t q, const bcgs_problem* p,
       c.ldr, c.d_info, &rq.plan);
   if (st != BCGS_OK) return st;
   rq.footprint = footprint_of(c, rq.plan);
+  rq.est = estimate_seconds(c);
   {
     std::lock_guard<std::mutex> lock(q->mu);
     if (q->stop) return BCGS_ERR_ARG;

@@ -26,6 +26,7 @@
 // per step; every reduction is summed in a fixed order, so results are
 // identical run to run.
 #include "common.h"
+#include "tsqr_wave_impl.h"
 
 namespace bcgs {
 
@@ -294,31 +295,13 @@ __global__ __launch_bounds__(kT) void node_kernel(
   }
 }
 
-// downward: C_child = Qnode_parent[child block] * C_parent (s x s,
-// column-major); the root's C is the identity.
+// downward pass (the body is shared with the s <= 16 TSQR)
 __global__ __launch_bounds__(kT) void down_kernel(
     const double* __restrict__ qpar, const double* __restrict__ cpar,
     int64_t nchild, int fan, int s, double* __restrict__ cchild,
     int parent_is_root) {
-  const int64_t child = blockIdx.x;
-  const int64_t p = child / fan;
-  const int idx_in = (int)(child % fan);
-  const int rows = fan * s;
-  const double* qb = qpar + (size_t)p * rows * s + (size_t)idx_in * s;
-  const double* cp = cpar + (size_t)p * s * s;
-  double* out = cchild + (size_t)child * s * s;
-  for (int e = threadIdx.x; e < s * s; e += kT) {
-    const int c = e / s, r = e % s;
-    double acc;
-    if (parent_is_root) {
-      acc = qb[(size_t)c * rows + r];
-    } else {
-      acc = 0.0;
-      for (int k = 0; k < s; ++k)
-        acc += qb[(size_t)k * rows + r] * cp[c * s + k];
-    }
-    out[e] = acc;
-  }
+  tsqr_down_body(qpar, cpar, nchild, fan, s, cchild, parent_is_root,
+                 blockIdx.x);
 }
 
 // apply pass: explicit Q rows of every chunk, optionally in place
@@ -395,6 +378,11 @@ void tsqr_down(const TsqrPlan& tp, double* ws, hipStream_t st) {
   const double ss = (double)s * s;
   for (int l = tp.levels; l >= 1; --l) {
     const double n = (double)tp.nodes[l - 1];
+    if (rec_active()) {
+      rec_tsqr_down(ws + tp.q_off[l], ws + tp.c_off[l], tp.nodes[l - 1], fan,
+                    s, ws + tp.c_off[l - 1], l == tp.levels ? 1 : 0);
+      continue;
+    }
     prof_begin(BCGS_KERNEL_TSQR_DOWN, l, 8.0 * n * ss * 2, 2.0 * n * ss * s);
     hipLaunchKernelGGL(tq::down_kernel, dim3((unsigned)tp.nodes[l - 1]),
                        dim3(kThreads), 0, st, ws + tp.q_off[l],
@@ -410,6 +398,10 @@ static hipError_t launch_tsqr_s(const TsqrPlan& tp, const T* v, int64_t ldv,
                                 T* dst, int64_t ldd, int64_t m, double* ws,
                                 double* r_out, int64_t r_rs, int64_t r_cs,
                                 int32_t* syncs, hipStream_t st) {
+  if (rec_active()) {
+    rec_unsupported();
+    return hipSuccess;
+  }
   const int s = tp.s, fan = tp.fan;
   const size_t lds = (size_t)tq::lds_doubles(s) * sizeof(double);
   const double ss = (double)s * s, esz = sizeof(T);

@@ -20,351 +20,10 @@
 //   H_1 ... H_s E = E - V W,   w_i = tau_i (v_i^T E - sum_{k>i} (v_i^T v_k) w_k)
 // (rows w_i of W, i = s-1 down to 0), where v_i^T v_k come out of the same
 // wave sums as the factorization's dot products.
-#include "common.h"
+#include "tsqr_wave_impl.h"
 
 namespace bcgs {
-namespace tw {
 
-template <int S>
-struct Geo {
-  static constexpr int R = 64 / S;       // rows per lane
-  static constexpr int L = 64 * R;       // rows per chunk
-  static constexpr int P =               // reduction slots (power of two)
-      S <= 1 ? 1 : S <= 2 ? 2 : S <= 4 ? 4 : S <= 8 ? 8 : 16;
-  static constexpr int SH =              // slot c ends in lane c << SH
-      P == 1 ? 6 : P == 2 ? 5 : P == 4 ? 4 : P == 8 ? 3 : 2;
-};
-
-constexpr int kRowMirror = 0x140;
-constexpr int kRowHalfMirror = 0x141;
-constexpr int kQuadXor1 = 0xB1;          // quad_perm [1, 0, 3, 2]
-constexpr int kQuadXor2 = 0x4E;          // quad_perm [2, 3, 0, 1]
-
-template <int CTRL>
-__device__ __forceinline__ double dpp(double x) {
-  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), CTRL, 0xf,
-                                             0xf, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), CTRL, 0xf,
-                                             0xf, false);
-  return __hiloint2double(hi, lo);
-}
-
-// a + b after exchanging lanes 32..63 of a with lanes 0..31 of b: lanes
-// 0..31 get a(l) + a(l + 32), lanes 32..63 get b(l - 32) + b(l).
-__device__ __forceinline__ double swap32_sum(double a, double b) {
-  const auto l = __builtin_amdgcn_permlane32_swap(
-      (unsigned)__double2loint(a), (unsigned)__double2loint(b), false, false);
-  const auto h = __builtin_amdgcn_permlane32_swap(
-      (unsigned)__double2hiint(a), (unsigned)__double2hiint(b), false, false);
-  return __hiloint2double((int)h[0], (int)l[0]) +
-         __hiloint2double((int)h[1], (int)l[1]);
-}
-
-// the same within each half wave, for lanes 16 apart
-__device__ __forceinline__ double swap16_sum(double a, double b) {
-  const auto l = __builtin_amdgcn_permlane16_swap(
-      (unsigned)__double2loint(a), (unsigned)__double2loint(b), false, false);
-  const auto h = __builtin_amdgcn_permlane16_swap(
-      (unsigned)__double2hiint(a), (unsigned)__double2hiint(b), false, false);
-  return __hiloint2double((int)h[0], (int)l[0]) +
-         __hiloint2double((int)h[1], (int)l[1]);
-}
-
-__device__ __forceinline__ double bcast(double y, int lane) {
-  const int lo = __builtin_amdgcn_readlane(__double2loint(y), lane);
-  const int hi = __builtin_amdgcn_readlane(__double2hiint(y), lane);
-  return __hiloint2double(hi, lo);
-}
-
-// Wave sums of the P slots v[0..P-1].  On return slot c's total is held by
-// lane c << SH (and the other lanes of its group); read it with bcast().
-// Lane bits 5, 4, 3, 2 split the slots (the partner lane keeps the other
-// half of the slots); the remaining bits are summed over directly.
-template <int P>
-__device__ __forceinline__ double wave_sums(double (&v)[P]) {
-  const int lane = threadIdx.x & 63;
-  if constexpr (P >= 2) {
-#pragma unroll
-    for (int i = 0; i < P / 2; ++i) v[i] = swap32_sum(v[i], v[i + P / 2]);
-  }
-  if constexpr (P >= 4) {
-#pragma unroll
-    for (int i = 0; i < P / 4; ++i) v[i] = swap16_sum(v[i], v[i + P / 4]);
-  }
-  if constexpr (P >= 8) {
-    const bool hi = (lane >> 3) & 1;
-#pragma unroll
-    for (int i = 0; i < P / 8; ++i) {
-      const double send = hi ? v[i] : v[i + P / 8];
-      const double keep = hi ? v[i + P / 8] : v[i];
-      v[i] = keep + dpp<kRowMirror>(send);
-    }
-  }
-  if constexpr (P >= 16) {
-    const bool hi = (lane >> 2) & 1;
-#pragma unroll
-    for (int i = 0; i < P / 16; ++i) {
-      const double send = hi ? v[i] : v[i + P / 16];
-      const double keep = hi ? v[i + P / 16] : v[i];
-      v[i] = keep + dpp<kRowHalfMirror>(send);
-    }
-  }
-  double y = v[0];
-  y += dpp<kQuadXor1>(y);
-  y += dpp<kQuadXor2>(y);
-  if constexpr (P < 16) y += dpp<kRowHalfMirror>(y);
-  if constexpr (P < 8) y += dpp<kRowMirror>(y);
-  if constexpr (P < 4) y = swap16_sum(y, y);
-  if constexpr (P < 2) y = swap32_sum(y, y);
-  return y;
-}
-
-// LDS ordering between the lanes of one wave (no workgroup barrier).
-__device__ __forceinline__ void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-// Householder QR of the chunk in a[][] (LAPACK convention: H_j = I - tau_j
-// v_j v_j^T, v_j(j) = 1, beta_j = -sign(alpha_j) ||x_j||).  Afterwards the
-// rows < S of a[0][] hold R (lane l: row l) and the entries below the
-// diagonal hold the reflectors.  With z != nullptr (lane 0 writes) the
-// products v_i^T v_j (i < j) go to z[i * S + j].
-template <int S>
-__device__ __forceinline__ void factor(double (&a)[Geo<S>::R][S],
-                                       double (&tau)[S], double* z) {
-  using Gm = Geo<S>;
-  constexpr int R = Gm::R, P = Gm::P, SH = Gm::SH;
-  const int lane = threadIdx.x & 63;
-#pragma unroll
-  for (int j = 0; j < S; ++j) {
-    double pn[1] = {0.0};
-#pragma unroll
-    for (int k = 0; k < R; ++k) {
-      const double x = a[k][j];
-      pn[0] += (k > 0 || lane > j) ? x * x : 0.0;
-    }
-    const double sigma2 = bcast(wave_sums<1>(pn), 0);
-    const double alpha = bcast(a[0][j], j);
-    double t = 0.0, scal = 0.0, beta = alpha;
-    if (sigma2 != 0.0) {
-      const double nrm = sqrt(alpha * alpha + sigma2);
-      beta = alpha >= 0.0 ? -nrm : nrm;
-      t = (beta - alpha) / beta;
-      scal = 1.0 / (alpha - beta);
-    }
-    tau[j] = t;
-    if (z != nullptr && lane == 0) z[j * S + j] = t;
-    double v[R];
-#pragma unroll
-    for (int k = 0; k < R; ++k) {
-      if (k == 0) {
-        v[0] = lane > j ? a[0][j] * scal : (lane == j ? 1.0 : 0.0);
-        a[0][j] = lane > j ? v[0] : (lane == j ? beta : a[0][j]);
-      } else {
-        v[k] = a[k][j] * scal;
-        a[k][j] = v[k];
-      }
-    }
-    if constexpr (S > 1) {
-      double d[P];
-#pragma unroll
-      for (int c = 0; c < P; ++c) {
-        double acc = 0.0;
-        if (c < S && c != j && (c > j || z != nullptr)) {
-#pragma unroll
-          for (int k = 0; k < R; ++k) acc += v[k] * a[k][c];
-        }
-        d[c] = acc;
-      }
-      const double y = wave_sums<P>(d);
-#pragma unroll
-      for (int c = j + 1; c < S; ++c) {
-        const double tw = t * bcast(y, c << SH);
-#pragma unroll
-        for (int k = 0; k < R; ++k) a[k][c] -= tw * v[k];
-      }
-      if (z != nullptr) {
-#pragma unroll
-        for (int c = 0; c < j; ++c) {
-          const double zc = bcast(y, c << SH);
-          if (lane == 0) z[c * S + j] = zc;
-        }
-      }
-    }
-  }
-}
-
-template <typename T, int S>
-__device__ __forceinline__ void load_chunk(const T* __restrict__ v,
-                                           int64_t ldv, int64_t m,
-                                           int64_t row0,
-                                           double (&a)[Geo<S>::R][S]) {
-  const int lane = threadIdx.x & 63;
-#pragma unroll
-  for (int k = 0; k < Geo<S>::R; ++k) {
-    const int64_t row = row0 + lane + 64 * k;
-#pragma unroll
-    for (int c = 0; c < S; ++c)
-      a[k][c] = row < m ? static_cast<double>(v[(int64_t)c * ldv + row]) : 0.0;
-  }
-}
-
-// Explicit rows of H_1 ... H_s [C; 0], handed row block by row block to
-// store(k, c, value) (rows lane + 64 k, column c).  a[][] holds the factored
-// chunk and is left unchanged; C (s x s) is read from cc (column-major) or
-// is the identity when cc == nullptr.  lds: this wave's own 4 S^2 doubles,
-// z and tau already filled by factor().  The s x s work runs on lanes < S
-// with its operands in LDS; only the final product E - V W touches the
-// register-resident rows.
-template <int S, typename Store>
-__device__ __forceinline__ void form_q(const double (&a)[Geo<S>::R][S],
-                                       const double* __restrict__ cc,
-                                       double* lds, Store store) {
-  constexpr int R = Geo<S>::R;
-  const int lane = threadIdx.x & 63;
-  double* z = lds;                   // z[i * S + k] = v_i^T v_k, i < k
-  double* vt = lds + S * S;          // vt[r * S + i] = v_i(r), r < S
-  double* wl = lds + 2 * S * S;      // W, row-major
-  double* cl = lds + 3 * S * S;      // C, row-major; tau in z's diagonal
-  if (lane < S) {
-#pragma unroll
-    for (int i = 0; i < S; ++i) {
-      vt[lane * S + i] = i < lane ? a[0][i] : (i == lane ? 1.0 : 0.0);
-      cl[lane * S + i] = cc ? cc[i * S + lane] : (i == lane ? 1.0 : 0.0);
-    }
-  }
-  wave_sync();
-  if (lane < S) {
-    const int c = lane;
-#pragma unroll 1
-    for (int i = S - 1; i >= 0; --i) {
-      double u = cl[i * S + c];
-      for (int r = i + 1; r < S; ++r) u += vt[r * S + i] * cl[r * S + c];
-      for (int k = i + 1; k < S; ++k) u -= z[i * S + k] * wl[k * S + c];
-      wl[i * S + c] = z[i * S + i] * u;
-    }
-  }
-  wave_sync();
-#pragma unroll 1
-  for (int c = 0; c < S; ++c) {
-    double wc[S];
-#pragma unroll
-    for (int i = 0; i < S; ++i) wc[i] = wl[i * S + c];
-    const double e0 = lane < S ? cl[lane * S + c] : 0.0;
-#pragma unroll
-    for (int k = 0; k < R; ++k) {
-      double q = k == 0 ? e0 : 0.0;
-#pragma unroll
-      for (int i = 0; i < S; ++i) {
-        const double vi =
-            k > 0 ? a[k][i] : (i < lane ? a[0][i] : (i == lane ? 1.0 : 0.0));
-        q -= vi * wc[i];
-      }
-      store(k, c, q);
-    }
-  }
-}
-
-// leaf pass: R factor of every chunk (column-major s x s)
-template <typename T, int S>
-__global__ __launch_bounds__(256) void leaf_kernel(
-    const T* __restrict__ v, int64_t ldv, int64_t m, int64_t nchunks,
-    double* __restrict__ rleaf) {
-  const int64_t chunk = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (chunk >= nchunks) return;
-  const int lane = threadIdx.x & 63;
-  double a[Geo<S>::R][S], tau[S];
-  load_chunk<T, S>(v, ldv, m, chunk * Geo<S>::L, a);
-  factor<S>(a, tau, nullptr);
-  if (lane < S) {
-    double* out = rleaf + (size_t)chunk * S * S;
-#pragma unroll
-    for (int c = 0; c < S; ++c) out[c * S + lane] = c >= lane ? a[0][c] : 0.0;
-  }
-}
-
-// one upward level: node stacks children [node*fan, ...) of nprev; stores
-// its R and its explicit Q (fan*s x s, column-major); the root normalizes
-// signs (R <- D R, Q <- Q D) and also writes R to r_out.
-template <int S>
-__global__ __launch_bounds__(256) void node_kernel(
-    const double* __restrict__ rprev, int64_t nprev, int fan, int64_t nnodes,
-    double* __restrict__ rcur, double* __restrict__ qcur, int is_root,
-    double* r_out, int64_t r_rs, int64_t r_cs, int32_t* syncs) {
-  __shared__ double lds[4][4 * S * S];
-  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int64_t node = (int64_t)blockIdx.x * 4 + wv;
-  if (node >= nnodes) return;
-  // the root completes the synchronization point of this TSQR
-  if (is_root && syncs != nullptr && lane == 0) *syncs += 1;
-  constexpr int R = Geo<S>::R;
-  const int64_t c0 = node * fan;
-  const int nch = (int)min((int64_t)fan, nprev - c0);
-  const int rows = fan * S;
-  double a[R][S], tau[S];
-#pragma unroll
-  for (int k = 0; k < R; ++k) {
-    const int i = lane + 64 * k;
-    const int ch = i / S, rr = i % S;
-#pragma unroll
-    for (int c = 0; c < S; ++c)
-      a[k][c] = (i < rows && ch < nch)
-                    ? rprev[(size_t)(c0 + ch) * S * S + (size_t)c * S + rr]
-                    : 0.0;
-  }
-  double* my = lds[wv];
-  factor<S>(a, tau, my);
-  double sgn[S];
-#pragma unroll
-  for (int c = 0; c < S; ++c)
-    sgn[c] = (is_root && bcast(a[0][c], c) < 0.0) ? -1.0 : 1.0;
-  if (lane < S) {
-    double* rn = rcur + (size_t)node * S * S;
-    double mine = 1.0;                  // sign of this lane's row of R
-#pragma unroll
-    for (int c = 0; c < S; ++c) mine = c == lane ? sgn[c] : mine;
-#pragma unroll
-    for (int c = 0; c < S; ++c) {
-      const double val = (c >= lane ? a[0][c] : 0.0) * mine;
-      rn[c * S + lane] = val;
-      if (is_root) r_out[lane * r_rs + c * r_cs] = val;
-    }
-  }
-  double* qn = qcur + (size_t)node * rows * S;
-  form_q<S>(a, nullptr, my, [&](int k, int c, double q) {
-    const int i = lane + 64 * k;
-    double d = 1.0;
-#pragma unroll
-    for (int cc = 0; cc < S; ++cc) d = cc == c ? sgn[cc] : d;
-    if (i < rows) qn[(size_t)c * rows + i] = q * d;
-  });
-}
-
-// apply pass: explicit Q rows of every chunk, optionally in place
-template <typename T, int S>
-__global__ __launch_bounds__(256) void apply_kernel(
-    const T* v, int64_t ldv, int64_t m, int64_t nchunks,
-    const double* __restrict__ cleaf, T* dst, int64_t ldd) {
-  __shared__ double lds[4][4 * S * S];
-  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int64_t chunk = (int64_t)blockIdx.x * 4 + wv;
-  if (chunk >= nchunks) return;
-  constexpr int R = Geo<S>::R;
-  const int64_t row0 = chunk * Geo<S>::L;
-  double a[R][S], tau[S];
-  load_chunk<T, S>(v, ldv, m, row0, a);
-  double* my = lds[wv];
-  factor<S>(a, tau, my);
-  form_q<S>(a, cleaf + (size_t)chunk * S * S, my,
-            [&](int k, int c, double q) {
-              const int64_t row = row0 + lane + 64 * k;
-              if (row < m) dst[(int64_t)c * ldd + row] = static_cast<T>(q);
-            });
-}
-
-}  // namespace tw
 
 int wave_tsqr_rows(int s) { return s <= 16 ? 64 * (64 / s) : 0; }
 
@@ -379,6 +38,24 @@ static hipError_t launch_wave_tsqr_s(const TsqrPlan& tp, const T* v,
   const int fan = tp.fan;
   const double ss = (double)S * S, esz = sizeof(T);
   auto wgs = [](int64_t waves) { return dim3((unsigned)cdiv(waves, 4)); };
+  if (rec_active()) {
+    // the same kernels as steps of work items (binary64, s = 4, 8, 16)
+    if constexpr (sizeof(T) == 8 && (S == 4 || S == 8 || S == 16)) {
+      rec_tsqr_leaf(S, v, ldv, m, tp.nchunks, ws + tp.r_off[0],
+                    cdiv(tp.nchunks, 4));
+      for (int l = 1; l <= tp.levels; ++l)
+        rec_tsqr_node(S, ws + tp.r_off[l - 1], tp.nodes[l - 1], fan,
+                      tp.nodes[l], ws + tp.r_off[l], ws + tp.q_off[l],
+                      l == tp.levels ? 1 : 0, r_out, r_rs, r_cs, syncs,
+                      cdiv(tp.nodes[l], 4));
+      tsqr_down(tp, ws, st);
+      rec_tsqr_apply(S, v, ldv, m, tp.nchunks, ws + tp.c_off[0], dst, ldd,
+                     cdiv(tp.nchunks, 4));
+    } else {
+      rec_unsupported();
+    }
+    return hipSuccess;
+  }
   prof_begin(BCGS_KERNEL_TSQR_LEAF, 0, esz * m * S, 2.0 * m * ss);
   hipLaunchKernelGGL((tw::leaf_kernel<T, S>), wgs(tp.nchunks), dim3(256), 0,
                      st, v, ldv, m, tp.nchunks, ws + tp.r_off[0]);

@@ -6,6 +6,7 @@ profiles/.
            <write_dir> <prefix> "<cmd>"
     python -m paper_2507_21791_amd.prof_summary requests <read_dir>
            <write_dir> "<cmd>"
+    python -m paper_2507_21791_amd.prof_summary sq <dir> "<cmd>" ...
 
 `trace` reads <dir>/<prefix>_kernel_trace.csv (a --kernel-trace run) and
 prints per-kernel launch counts and durations for this library's kernels
@@ -37,7 +38,7 @@ def short_name(name):
     n = re.sub(r"\(.*", "", name)
     n = n.replace("void ", "").replace("bcgs::", "")
     n = n.replace("p16::", "").replace("tq::", "tsqr_")
-    n = n.replace("tw::", "tsqr_wave_")
+    n = n.replace("tw::", "tsqr_wave_").replace("ck::", "check_")
     return n.strip()
 
 
@@ -163,7 +164,7 @@ def _dispatches(d, names):
     f = [x for x in os.listdir(d) if x.endswith("counter_collection.csv")][0]
     out = OrderedDict()
     for r in csv.DictReader(open(os.path.join(d, f))):
-        if r["Counter_Name"] not in names:
+        if names is not None and r["Counter_Name"] not in names:
             continue
         k = out.setdefault(int(r["Dispatch_Id"]),
                            (r["Kernel_Name"], int(r["Grid_Size"]), {}))
@@ -209,6 +210,46 @@ def requests(drd, dwrite, cmd):
     return "\n".join(out)
 
 
+def sq(dirs, cmds):
+    """Per-launch SQ counters of the library's streaming passes from one or
+    more --pmc runs (each run holds at most 8 SQ counters).  MFMA busy is
+    given as a share of the cycles of all SIMDs over the kernel's duration
+    (SQ_BUSY_CYCLES counts one per shader engine and cycle: 32 on this
+    GPU, each with 32 SIMDs), wait and issue counts per wave."""
+    per = defaultdict(lambda: defaultdict(list))
+    for d in dirs:
+        for i, (n, g, c) in _dispatches(d, None).items():
+            if ours(n) and "pass" in n:
+                for k, v in c.items():
+                    per[short_name(n)][k].append(v)
+    out = ["# rocprofv3 SQ counter summary of the streaming passes",
+           *[f"# command: {c}" for c in cmds],
+           "# per-launch means; busy = SQ_VALU_MFMA_BUSY_CYCLES / (1024 SIMDs"
+           " x SQ_BUSY_CYCLES / 32); wait_inst, wait_any: share of"
+           " SQ_WAVE_CYCLES; instructions per wave (SQ_WAVES waves)"]
+    for k, c in sorted(per.items()):
+        m = {kk: sum(v) / len(v) for kk, v in c.items()}
+        parts = [f"launches={len(next(iter(c.values())))}"]
+        if "SQ_VALU_MFMA_BUSY_CYCLES" in m and "SQ_BUSY_CYCLES" in m:
+            parts.append("mfma_busy=%.3f" % (m["SQ_VALU_MFMA_BUSY_CYCLES"] /
+                                            (1024 * m["SQ_BUSY_CYCLES"] / 32)))
+        for w in ("SQ_WAIT_INST_ANY", "SQ_WAIT_ANY"):
+            if w in m and "SQ_WAVE_CYCLES" in m:
+                parts.append("%s=%.3f" % (w.lower()[3:], m[w] /
+                                          m["SQ_WAVE_CYCLES"]))
+        if "SQ_WAVES" in m:
+            for w in ("SQ_INSTS_MFMA", "SQ_INSTS_VALU", "SQ_INSTS_SALU",
+                      "SQ_INSTS_LDS"):
+                if w in m:
+                    parts.append("%s/wave=%.0f" % (w.lower()[9:],
+                                                   m[w] / m["SQ_WAVES"]))
+        if "SQ_LDS_BANK_CONFLICT" in m:
+            parts.append("lds_bank_conflict=%.3g" % m["SQ_LDS_BANK_CONFLICT"])
+        out.append(k)
+        out.append("    " + "  ".join(parts))
+    return "\n".join(out)
+
+
 def main(argv):
     root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
     if argv[1] == "trace":
@@ -217,6 +258,9 @@ def main(argv):
         print(counters(argv[2], argv[3], argv[4], argv[5], root))
     elif argv[1] == "requests":
         print(requests(argv[2], argv[3], argv[4]))
+    elif argv[1] == "sq":
+        # sq <dir1> <cmd1> [<dir2> <cmd2> ...]
+        print(sq(argv[2::2], argv[3::2]))
     else:
         raise SystemExit(__doc__)
 

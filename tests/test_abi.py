@@ -196,9 +196,10 @@ def test_tuning_set_every_variant(variant):
 
 
 def test_queue_struct_layouts():
-    assert ctypes.sizeof(bcgs.QueueConfig) == 32
+    assert ctypes.sizeof(bcgs.QueueConfig) == 40
     assert bcgs.QueueConfig.output_arena_bytes.offset == 16
     assert bcgs.QueueConfig.retry_variant.offset == 28
+    assert bcgs.QueueConfig.admission.offset == 32
     assert ctypes.sizeof(bcgs.RequestStats) == 88
     assert bcgs.RequestStats.info.offset == 8
     assert bcgs.RequestStats.t_done.offset == 56
@@ -206,12 +207,13 @@ def test_queue_struct_layouts():
     assert bcgs.RequestStats.attempts.offset == 84
 
 
-@pytest.mark.parametrize("budget,inflight,retry", [
-    (0, 4, (0, 0)), (1 << 30, 0, (0, 0)), (1 << 30, 17, (0, 0)),
-    (1 << 30, 4, (1, 9))])
-def test_queue_bad_config_rejected(budget, inflight, retry):
+@pytest.mark.parametrize("budget,inflight,retry,admission", [
+    (0, 4, (0, 0), 0), (1 << 30, 0, (0, 0), 0), (1 << 30, 17, (0, 0), 0),
+    (1 << 30, 4, (1, 9), 0), (1 << 30, 4, (0, 0), 2),
+    (1 << 30, 4, (0, 0), -1)])
+def test_queue_bad_config_rejected(budget, inflight, retry, admission):
     L = bcgs.lib()
-    cfg = bcgs.QueueConfig(budget, inflight, 0, 0, *retry)
+    cfg = bcgs.QueueConfig(budget, inflight, 0, 0, *retry, admission, 0)
     h = ctypes.c_void_p()
     assert L.bcgs_queue_create(ctypes.byref(cfg), ctypes.byref(h)) == \
         bcgs.BCGS_ERR_ARG
@@ -230,3 +232,30 @@ def test_queue_null_handles_rejected():
     assert L.bcgs_queue_wait(None, 1, ctypes.byref(out)) == bcgs.BCGS_ERR_ARG
     assert L.bcgs_queue_destroy(None) == bcgs.BCGS_ERR_ARG
     assert L.bcgs_queue_free_output(None, FAKE, None) == bcgs.BCGS_ERR_ARG
+
+
+def test_check_rejects_bad_arguments_before_enqueue():
+    """bcgs_check validates shapes, leading dimensions, precision and the
+    workspace before any device call (fake pointers are never touched)."""
+    L = bcgs.lib()
+    f = ctypes.c_void_p
+    m, n = 5000, 64
+    need = L.bcgs_check_workspace_size(m, n)
+    assert need >= m * n * 8
+    assert L.bcgs_check_workspace_size(10, 20) == 0      # m < n
+    assert L.bcgs_check_workspace_size(10, 0) == 0
+
+    def call(m=m, n=n, ldx=m, ldq=m, ldr=n, prec=0, ldg=n, ws=0x7000000000,
+             nbytes=need, X=0x1000000000):
+        return L.bcgs_check(f(X), ldx, f(0x2000000000), ldq, f(0x3000000000),
+                            ldr, m, n, prec, f(0x4000000000), f(0x5000000000),
+                            f(0x6000000000), ldg, f(ws), nbytes, None)
+    assert call(X=0) == bcgs.BCGS_ERR_ARG
+    assert call(ldx=m - 1) == bcgs.BCGS_ERR_ARG
+    assert call(ldq=m - 1) == bcgs.BCGS_ERR_ARG
+    assert call(ldr=n - 1) == bcgs.BCGS_ERR_ARG
+    assert call(ldg=n - 1) == bcgs.BCGS_ERR_ARG
+    assert call(prec=5) == bcgs.BCGS_ERR_ARG
+    assert call(nbytes=need - 1) == bcgs.BCGS_ERR_ARG
+    assert call(ws=0x7000000008) == bcgs.BCGS_ERR_ARG
+    assert call(m=n - 1, ldx=n, ldq=n) == bcgs.BCGS_ERR_ARG
