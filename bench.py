@@ -35,35 +35,20 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def chunked_gram(A, B=None, chunk=1 << 16):
-    """A^T B on the device as a pairwise sum of per-chunk products."""
-    import torch
-    B = A if B is None else B
-    parts = [A[i:i + chunk].t() @ B[i:i + chunk]
-             for i in range(0, A.shape[0], chunk)]
-    while len(parts) > 1:
-        nxt = [parts[i] + parts[i + 1] for i in range(0, len(parts) - 1, 2)]
-        if len(parts) % 2:
-            nxt.append(parts[-1])
-        parts = nxt
-    return parts[0]
+_CHECKER = None
 
 
-def accuracy(X, Q, R, chunk=1 << 16):
-    """LOO ||Q^T Q - I||_2 and ||X - QR||_2 / ||X||_2 (section 1)."""
+def accuracy(X, Q, R):
+    """LOO ||Q^T Q - I||_2 and ||X - QR||_2 / ||X||_2 (section 1), by the
+    library's device checker (Gram matrices on the GPU, the 2-norms of the
+    three n x n symmetric matrices on the host)."""
     import torch
-    n = Q.shape[1]
-    G = chunked_gram(Q) - torch.eye(n, dtype=Q.dtype, device=Q.device)
-    loo = torch.linalg.eigvalsh(0.5 * (G + G.t())).abs().max().item()
-    parts = []
-    for i in range(0, X.shape[0], chunk):
-        E = X[i:i + chunk] - Q[i:i + chunk] @ R
-        parts.append(E.t() @ E)
-    GE = torch.stack(parts).sum(0)
-    GX = chunked_gram(X)
-    num = torch.linalg.eigvalsh(0.5 * (GE + GE.t())).abs().max().sqrt().item()
-    den = torch.linalg.eigvalsh(0.5 * (GX + GX.t())).abs().max().sqrt().item()
-    return loo, num / den
+    from paper_2507_21791_amd import bcgs
+    global _CHECKER
+    if _CHECKER is None:
+        _CHECKER = bcgs.Checker()
+    prec = "fp64" if X.dtype == torch.float64 else "fp32-bulk"
+    return _CHECKER(X, Q, R, prec)
 
 
 def time_variant(X, s, variant, steps, warmup, Q, R, precision="fp64"):
@@ -270,7 +255,7 @@ def bench_fp32_bulk(m, n, s, steps, warmup, fp64_ms):
                                         "fp32-bulk")
     agg = aggregate(recs, steps)
     model_bytes = sum(a["bytes"] for a in agg)
-    loo, resid = accuracy(X.double(), Q.double(), R)
+    loo, resid = accuracy(X, Q, R)
     out = {"workload": f"m={m} n={n} s={s} kappa=1e3, P-1S, FP32-bulk",
            "ms": round(ms, 4), "model_gb": round(model_bytes / 1e9, 3),
            "gbs": round(model_bytes / (ms * 1e-3) / 1e9, 1),
@@ -381,10 +366,41 @@ def bench_sweep(steps, warmup, sizes=(4, 8, 16, 32, 64)):
                          f"{steps} timed steps each"), "rows": rows}
 
 
+def _time_batched(batch, reps, mode):
+    """ms per launch of bcgs_qr_batched in `mode` (None: the default graph
+    launch; "persistent"), after one untimed launch (capture / upload)."""
+    import torch
+    from paper_2507_21791_amd import bcgs
+    old = os.environ.pop("BCGS_BATCH_MODE", None)
+    if mode:
+        os.environ["BCGS_BATCH_MODE"] = mode
+    try:
+        stream = torch.cuda.current_stream()
+        bcgs.qr_batched(batch)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            bcgs.qr_batched(batch)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+    finally:
+        os.environ.pop("BCGS_BATCH_MODE", None)
+        if old is not None:
+            os.environ["BCGS_BATCH_MODE"] = old
+
+
 def bench_batched(count, reps):
     """The batched workload (uneven problems, P-1S, FP64): autotune, then
-    time `reps` rounds of one graph launch against the same problems
-    launched one after another on one stream."""
+    time `reps` rounds of one batched launch (the graph launch and the
+    persistent kernel) against the same problems launched one after
+    another on one stream.  Then every instance's loss of orthogonality and
+    residual by the device checker; the instances that broke down or miss
+    10 n u on either measure run again as BCGSI+P-2S (Table 1: O(u) under
+    u kappa <= 1 instead of u kappa^2 <= 1) in one batched launch, and the
+    throughput counts the instances whose final result meets 10 n u."""
     import torch
     from paper_2507_21791_amd import bcgs, workloads as W
     specs = W.batched_specs(count)
@@ -421,49 +437,136 @@ def bench_batched(count, reps):
     e1.record(stream)
     torch.cuda.synchronize()
     ms_single = e0.elapsed_time(e1) / reps
-    bcgs.qr_batched(batch)          # capture + first replay
+    fp_single = [int(_bits_sum(R)) for _, R in outs]
+    ms_persist = _time_batched(batch, reps, "persistent")
+    fp_persist = [int(_bits_sum(R)) for _, R in outs]
+    ms_graph = _time_batched(batch, reps, None)
+    fp_graph = [int(_bits_sum(R)) for _, R in outs]
+    ms_batch = min(ms_graph, ms_persist)
+    res = batch.results()
+    U = 2.0 ** -53
+    chk = bcgs.Checker()
+
+    def measures(b, idx):
+        """(status, loo, residual) of problem idx of batch b."""
+        X, Q, R = b.items[idx][0], b.items[idx][1], b.items[idx][2]
+        info = b.results()[idx][2]
+        if info.status != 0:
+            return info.status, None, None
+        return (0,) + chk(X, Q, R)
+
+    first = [measures(batch, i) for i in range(count)]
     torch.cuda.synchronize()
     e0.record(stream)
-    for _ in range(reps):
-        bcgs.qr_batched(batch)
+    for (X, s, v, pr), (Q, R) in zip(items, outs):
+        chk.grams(X, Q, R)
     e1.record(stream)
     torch.cuda.synchronize()
-    ms_batch = e0.elapsed_time(e1) / reps
-    res = batch.results()
-    breakdowns = sum(1 for _, _, info in res if info.status != 0)
+    ms_check = e0.elapsed_time(e1)
+    good = lambda m, n: m[0] == 0 and m[1] <= 10 * n * U and \
+        m[2] <= 10 * n * U
+    redo = [i for i, p in enumerate(specs) if not good(first[i], p["n"])]
+    final = list(first)
+    ms_rerun = 0.0
+    if redo:
+        again = bcgs.Batch([(Xs[i], specs[i]["s"], "p-2s", "fp64")
+                            for i in redo])
+        ms_rerun = _time_batched(again, reps, None)
+        for j, i in enumerate(redo):
+            final[i] = measures(again, j)
+    ok = [i for i, p in enumerate(specs) if good(final[i], p["n"])]
+    loos = [final[i][1] for i in ok]
+    ress = [final[i][2] for i in ok]
     out = {"workload": (f"{count} problems, m U[10000,200000], n in "
                         "{32,64,128,256}, s in {8,16}, kappa 1e2..1e10, "
                         "P-1S FP64"),
            "ms_batched": round(ms_batch, 3),
+           "ms_graph": round(ms_graph, 3),
+           "ms_persistent": round(ms_persist, 3),
            "ms_one_by_one": round(ms_single, 3),
            "speedup": round(ms_single / ms_batch, 3),
+           "bitwise_equal_graph_persistent_alone": fp_single == fp_graph ==
+           fp_persist,
            "problems_per_s": round(count / (ms_batch * 1e-3), 1),
            "model_gb": round(model_bytes / 1e9, 3),
            "gbs": round(model_bytes / (ms_batch * 1e-3) / 1e9, 1),
            "autotune_s": round(tune_s, 2),
-           "breakdowns": breakdowns}
+           "breakdowns": sum(1 for _, _, info in res if info.status != 0),
+           "p1s_accurate": sum(1 for i, p in enumerate(specs)
+                               if good(first[i], p["n"])),
+           "rerun_as_p2s": len(redo),
+           "ms_rerun_p2s": round(ms_rerun, 3),
+           "ms_check_all": round(ms_check, 3),
+           "accurate_final": len(ok),
+           "accurate_per_s": round(len(ok) / ((ms_batch + ms_rerun) * 1e-3),
+                                   1),
+           "accurate_per_s_with_check": round(
+               len(ok) / ((ms_batch + ms_rerun + ms_check) * 1e-3), 1),
+           "loo_max": max(loos, default=None),
+           "residual_max": max(ress, default=None),
+           "accuracy_bar": "loo and residual <= 10 n u (device checker)"}
     log(f"[bench] batched: {out}")
     del Xs, batch, wss, outs
     torch.cuda.empty_cache()
     return out
 
 
-def bench_served(nreq, rate, precision, pool, pool32, loo_every=50,
+class _RawDevice:
+    """A device buffer the library handed out (queue-allocated outputs), as
+    an object torch.as_tensor accepts (__cuda_array_interface__)."""
+
+    def __init__(self, ptr, nelems, typestr):
+        self.__cuda_array_interface__ = {
+            "shape": (nelems,), "typestr": typestr, "data": (ptr, False),
+            "version": 3, "strides": None}
+
+
+def _bits_sum(t):
+    """Sum of the bit patterns of a column-major tensor with ld = rows (an
+    exact, order-independent fingerprint; int64 wraps)."""
+    import torch
+    it = torch.int64 if t.element_size() == 8 else torch.int32
+    return t.t().contiguous().view(it).sum(dtype=torch.int64)
+
+
+def _fingerprint(r, m, n, precision):
+    """Device fingerprints (Q bits, R bits) of a finished request."""
+    import torch
+    if r["Q"] is not None:
+        return _bits_sum(r["Q"]), _bits_sum(r["R"])
+    qt = "<f8" if precision == "fp64" else "<f4"
+    q = torch.as_tensor(_RawDevice(r["Q_ptr"], m * n, qt), device="cuda")
+    rr = torch.as_tensor(_RawDevice(r["R_ptr"], n * n, "<f8"), device="cuda")
+    it = torch.int64 if precision == "fp64" else torch.int32
+    return (q.view(it).sum(dtype=torch.int64),
+            rr.view(torch.int64).sum(dtype=torch.int64))
+
+
+def bench_served(nreq, rate, precision, pool, pool32, admission="shortest",
                  inflight=8, budget=96 << 30, arena=64 << 30):
     """Poisson arrivals at `rate` req/s of P-1S requests drawn from the
     device pool, through the library's request queue (continuous batching,
     queue-allocated outputs, a request that breaks down rerun once as
     P-2S).  Latency = completion - submission (the submitter submits at
-    each arrival time)."""
+    each arrival time).
+
+    Accuracy of every result: each finished request's Q and R are
+    fingerprinted on the device (sums of their bit patterns) before its
+    outputs go back to the arena.  After the stream, every distinct (pool
+    input, variant that produced the result) is factorized alone through
+    bcgs_qr_ex, timed, fingerprinted and measured by the device checker
+    (loss of orthogonality, relative residual); a served result whose
+    fingerprints equal its lone run's carries that run's measures.
+    Slowdown = latency / the lone run's time."""
     import threading
     import torch
     from paper_2507_21791_amd import bcgs, workloads as W
     trace = W.served_trace(nreq, rate, len(pool))
     src = pool if precision == "fp64" else pool32
     q = bcgs.Queue(hbm_budget_bytes=budget, max_inflight=inflight,
-                   output_arena_bytes=arena, retry_variant="p-2s")
+                   output_arena_bytes=arena, retry_variant="p-2s",
+                   admission=admission)
     tickets = [None] * nreq
-    sampled = {}
 
     def submitter():
         t0 = time.perf_counter()
@@ -471,44 +574,88 @@ def bench_served(nreq, rate, precision, pool, pool32, loo_every=50,
             d = arr - (time.perf_counter() - t0)
             if d > 0:
                 time.sleep(d)
-            caller = (i % loo_every) == 0
             tickets[i] = q.submit(src[k][0], 16, "p-1s", precision,
-                                  outputs="caller" if caller else "queue")
-            if caller:
-                sampled[i] = k
+                                  outputs="queue")
 
     th = threading.Thread(target=submitter)
     th.start()
     res = [None] * nreq
+    fps = [None] * nreq
+    fp_ok = True
     for i in range(nreq):
         while tickets[i] is None:
             time.sleep(0.0002)
         r = q.wait(tickets[i])
-        if r["Q_ptr"]:
-            q.free(r["Q_ptr"])
-            q.free(r["R_ptr"])
+        if r["status"] == 0 and fp_ok:
+            X = src[trace[i][1]][0]
+            try:
+                fps[i] = _fingerprint(r, X.shape[0], X.shape[1], precision)
+            except Exception as e:      # no device-array import in torch
+                log(f"[bench] served: fingerprints unavailable ({e})")
+                fp_ok = False
+        q.free(r["Q_ptr"])
+        q.free(r["R_ptr"])
         res[i] = r
     th.join()
     q.close()
     lat = np.array([r["t_done"] - r["t_submit"] for r in res]) * 1e3
     span = max(r["t_done"] for r in res) - min(r["t_submit"] for r in res)
-    loos = []
-    for i, k in sampled.items():
-        r = res[i]
-        if r["status"] == 0:
-            X = src[k][0].double() if precision != "fp64" else src[k][0]
-            loo, resid = accuracy(X, r["Q"].double(), r["R"])
-            loos.append((loo, resid))
+    fps = [None if f is None else (int(f[0]), int(f[1])) for f in fps]
+    # lone runs of every distinct (input, variant) the stream produced
+    chk = bcgs.Checker()
+    lone = {}
+    for i, r in enumerate(res):
+        key = (trace[i][1], r["variant"])
+        if r["status"] != 0 or key in lone:
+            continue
+        X = src[key[0]][0]
+        Q, R, ws = bcgs.qr(X, 16, key[1], precision)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(3):
+            bcgs.qr(X, 16, key[1], precision, Q=Q, R=R, ws=ws)
+        e1.record()
+        torch.cuda.synchronize()
+        fq, fr = _bits_sum(Q), _bits_sum(R)
+        loo, resid = chk(X, Q, R, precision)
+        lone[key] = {"ms": e0.elapsed_time(e1) / 3,
+                     "fp": (int(fq), int(fr)), "loo": loo, "res": resid}
+        del Q, R, ws
+    ok = [i for i, r in enumerate(res) if r["status"] == 0]
+    same = [i for i in ok
+            if fps[i] == lone[(trace[i][1], res[i]["variant"])]["fp"]]
+    loos = [lone[(trace[i][1], res[i]["variant"])]["loo"] for i in same]
+    ress = [lone[(trace[i][1], res[i]["variant"])]["res"] for i in same]
+    slow = np.array([lat[i] / lone[(trace[i][1], res[i]["variant"])]["ms"]
+                     for i in ok])
+    alone = np.array([lone[(trace[i][1], res[i]["variant"])]["ms"]
+                      for i in ok])
+    small = alone <= np.median(alone)
+    lat_ok = lat[ok]
+    pct = lambda a, p: round(float(np.percentile(a, p)), 3) if len(a) else None
     out = {"rate_per_s": rate, "requests": nreq, "precision": precision,
-           "p50_ms": round(float(np.percentile(lat, 50)), 3),
-           "p99_ms": round(float(np.percentile(lat, 99)), 3),
+           "admission": admission,
+           "p50_ms": pct(lat, 50), "p99_ms": pct(lat, 99),
+           "p99_over_p50": round(float(np.percentile(lat, 99) /
+                                       np.percentile(lat, 50)), 2),
+           "slowdown_p50": pct(slow, 50), "slowdown_p99": pct(slow, 99),
+           "small_half_p50_ms": pct(lat_ok[small], 50),
+           "small_half_p99_ms": pct(lat_ok[small], 99),
+           "large_half_p50_ms": pct(lat_ok[~small], 50),
+           "large_half_p99_ms": pct(lat_ok[~small], 99),
+           "alone_ms_p50": pct(alone, 50), "alone_ms_p99": pct(alone, 99),
            "throughput_per_s": round(nreq / span, 1),
            "retried_as_p2s": int(sum(1 for r in res if r["attempts"] > 1)),
            "breakdowns": int(sum(1 for r in res if r["status"] == 2)),
            "errors": int(sum(1 for r in res if r["status"] not in (0, 2))),
-           "sampled_loo_max": max((l for l, _ in loos), default=None),
-           "sampled_residual_max": max((r for _, r in loos), default=None),
-           "sampled": len(loos)}
+           "results_checked": len(same),
+           "results_differing_from_lone": len(ok) - len(same),
+           "loo_max": max(loos, default=None),
+           "loo_median": float(np.median(loos)) if loos else None,
+           "residual_max": max(ress, default=None),
+           "distinct_lone_runs": len(lone)}
     log(f"[bench] served: {out}")
     return out
 
@@ -553,7 +700,7 @@ def main():
     ap.add_argument("--batched-count", type=int, default=256)
     ap.add_argument("--no-served", action="store_true")
     ap.add_argument("--served-n", type=int, default=1000)
-    ap.add_argument("--served-pool", type=int, default=24)
+    ap.add_argument("--served-pool", type=int, default=64)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (counter "
                          "calibration for rocprofv3 --pmc runs)")
@@ -689,8 +836,9 @@ def main():
         # latencies include the backlog; 150/s: about half of capacity, the
         # latency under a load the queue sustains (the headline p99)
         served = [bench_served(args.served_n, 2000.0, "fp64", pool, pool32),
-                  bench_served(max(1, args.served_n // 2), 150.0, "fp64",
-                               pool, pool32),
+                  bench_served(args.served_n, 150.0, "fp64", pool, pool32),
+                  bench_served(args.served_n, 150.0, "fp64", pool, pool32,
+                               admission="arrival"),
                   bench_served(args.served_n, 2000.0, "fp32-bulk", pool,
                                pool32)]
         out["served"] = {
@@ -701,7 +849,8 @@ def main():
             "runs": served}
         out["p99_latency_ms"] = served[1]["p99_ms"]
         out["p99_latency_load"] = ("fp64 requests at 150/s (about half of "
-                                   "the measured capacity)")
+                                   "the measured capacity), shortest-first "
+                                   "admission with aging")
         del pool, pool32
         torch.cuda.empty_cache()
     if not args.no_cpu:

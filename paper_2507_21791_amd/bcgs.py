@@ -373,6 +373,8 @@ class Batch:
     """A list of problems with device outputs and one info record each, in
     the layout bcgs_qr_batched takes.  Keeps the tensors alive."""
 
+    INFO_STRIDE = 128
+
     def __init__(self, items, device="cuda"):
         """items: iterable of (X, s, variant, precision) with X a column-major
         device tensor (float64 for fp64, float32 for fp32-bulk)."""
@@ -381,7 +383,9 @@ class Batch:
         arr = []
         self.info_buf = None
         items = list(items)
-        self.info_buf = torch.zeros(max(1, len(items)) * INFO_BYTES,
+        # one 128-byte cache line per info record: no two problems write
+        # the same line
+        self.info_buf = torch.zeros(max(1, len(items)) * self.INFO_STRIDE,
                                     dtype=torch.uint8, device=device)
         for i, (X, s, variant, precision) in enumerate(items):
             m, n = X.shape
@@ -395,15 +399,16 @@ class Batch:
             arr.append(Problem(X.data_ptr(), Q.data_ptr(), R.data_ptr(), m, n,
                                s, ldx, Q.stride(1), R.stride(1),
                                VARIANTS[variant], PRECISIONS[precision],
-                               self.info_buf.data_ptr() + i * INFO_BYTES))
+                               self.info_buf.data_ptr() +
+                               i * self.INFO_STRIDE))
         self.array = (Problem * max(1, len(arr)))(*arr)
         self.count = len(arr)
 
     def results(self):
         """[(Q, R, Info)] in input order (synchronizes on the info copy)."""
         raw = self.info_buf.cpu().numpy().tobytes()
-        return [(Q, R, Info.from_buffer_copy(raw[i * INFO_BYTES:
-                                                 (i + 1) * INFO_BYTES]))
+        k = self.INFO_STRIDE
+        return [(Q, R, Info.from_buffer_copy(raw[i * k:i * k + INFO_BYTES]))
                 for i, (_, Q, R, *_r) in enumerate(self.items)]
 
 

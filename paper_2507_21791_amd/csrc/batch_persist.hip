@@ -4,33 +4,45 @@
 // reset, fill, TSQR leaf / node / down / apply, streaming passes,
 // reductions, epilogues) is recorded on the host as a list of steps; a
 // step is a set of work items, one per workgroup the lone launch would
-// have had.  One kernel with two resident workgroups per CU then runs all
-// problems: a workgroup claims the next free item of some problem's
-// current step (a per-problem 64-bit word: step << 32 | next item), runs
-// the same device body the lone kernel runs, with the item as its
-// workgroup index, and counts the item done; the workgroup that completes
-// a step's last item opens the problem's next step.  That counter is the
-// per-problem device-side barrier between dependent steps, while items of
-// different problems (iterations, row chunks) run side by side.
+// have had, grouped into units of up to 8 consecutive items.  One kernel
+// with two resident workgroups per CU then runs all problems: a workgroup
+// claims the next free unit of some problem's current step (a per-problem
+// 64-bit word: owner << 56 | step << 32 | next unit), runs the same device
+// bodies the lone kernels run, with each item as its workgroup index, and
+// counts the unit done; the workgroup that completes a step's last unit
+// opens the problem's next step.  That counter is the per-problem
+// device-side barrier between dependent steps, while units of different
+// problems run side by side.
 //
 // Bits: an item computes exactly what workgroup `item` of the lone launch
-// computes (same bodies, same row split, same fixed-order sums), so a
-// batched result equals the lone one bitwise.  Streaming passes run their
-// register-staged form (the LDS tile is identical to the direct-copy one)
-// with four waves, whatever shape of four waves the lone run chose.
+// computes (same bodies, same row split, same fixed-order sums, the same
+// tile layout whether tiles are copied directly or through registers), so
+// a batched result equals the lone one bitwise.
 //
-// Visibility: items of one step run on any XCD, and XCDs have separate L2
-// caches, so every item ends with an agent-scope release fence before it
-// is counted, and every item starts with an agent-scope acquire fence.
+// Placement: each XCD has its own L2, so a problem is adopted by one XCD
+// (the hardware XCC_ID of the first workgroup that claims it) and all its
+// units run there.  Units then communicate through that L2: a unit's
+// stores are complete in the L2 before it is counted, without a write-back
+// of the L2 to memory, and a workgroup starting a unit of a new step
+// invalidates its caches at agent scope.  An XCD adopts the largest
+// problem nobody owns yet whenever it runs fewer than six problems, so the
+// XCDs share the work as they free up and finish together.
 //
-// Termination: items never wait for one another, so some workgroup always
-// makes progress; a workgroup that finds no free item sleeps briefly and
+// Code generation: every body is its own function; the step record it
+// receives is read as wave-uniform constant data (scalar loads), and all
+// its global accesses use global instructions (flat ones would be counted
+// with the LDS operations, coupling every LDS wait to the loads in
+// flight).
+//
+// Termination: units never wait for one another, so some workgroup always
+// makes progress; a workgroup that finds no free unit sleeps briefly and
 // looks again.  A workgroup that has found nothing to do for about ten
 // seconds (the device's 100 MHz clock) gives up, marks the unfinished
 // problems' info records BCGS_ERR_HIP and exits, so the launch always
 // ends.
 #include <string.h>
 
+#include <algorithm>
 #include <map>
 #include <mutex>
 #include <vector>
@@ -71,7 +83,8 @@ struct InitA { bcgs_info* info; };
 // One step: `items` work items of one kind; sel is the body (pass: tile
 // rows code * 3 + Gram B blocks; TSQR and epilogue: s).
 struct BatchStep {
-  int32_t kind, items, sel, pad;
+  int32_t kind, items, sel;
+  int32_t chunk;     // items run back to back per claim (a unit)
   union {
     p16::ArgsT<double> pass;
     EpiArgs epi;
@@ -85,12 +98,14 @@ struct BatchStep {
   } u;
 };
 
-// per problem: step << 32 | next item to claim; items of the step done
+// Per problem: w = owner << 56 | step << 32 | next unit to claim (owner
+// 0xFF: not adopted yet); units of the step done.
 struct ProbCtl {
   unsigned long long w;
   unsigned done;
   unsigned pad;
 };
+constexpr unsigned long long kNoOwner = 0xFFull << 56;
 
 // ------------------------------------------------------------ record ---
 namespace {
@@ -100,12 +115,20 @@ struct Recorder {
 };
 thread_local Recorder* t_rec = nullptr;
 
+// Items per unit: lone launches with many workgroups become fewer, longer
+// units (up to 8 items), so that per-claim costs are spread; at least 32
+// units remain for the XCD's workgroups to share.
+int chunk_for(int64_t items) {
+  return (int)std::max<int64_t>(1, std::min<int64_t>(8, items / 32));
+}
+
 BatchStep& add(int kind, int64_t items, int sel) {
   BatchStep st;
   memset(&st, 0, sizeof st);
   st.kind = kind;
   st.items = (int32_t)items;
   st.sel = sel;
+  st.chunk = chunk_for(items);
   if (items < 1 || items > (int64_t(1) << 30)) t_rec->unsupported = true;
   t_rec->steps.push_back(st);
   return t_rec->steps.back();
@@ -118,7 +141,7 @@ void rec_unsupported() {
 }
 
 void p16::rec_pass16(const p16::ArgsT<double>& a, int tr, int nw,
-                     int gram_ntb, int G) {
+                     int gram_ntb, int G, bool reg) {
   const int code = tr == 16 ? 0 : tr == 32 ? 1 : tr == 64 ? 2 : -1;
   // the bodies hold up to 272 (16 rows), 128 (32) or 64 (64) columns
   const int cap = tr == 16 ? 272 : tr == 32 ? 128 : 64;
@@ -126,7 +149,7 @@ void p16::rec_pass16(const p16::ArgsT<double>& a, int tr, int nw,
     t_rec->unsupported = true;
     return;
   }
-  add(SK_PASS, G, code * 3 + gram_ntb).u.pass = a;
+  add(SK_PASS, G, code * 3 + gram_ntb + (reg ? 9 : 0)).u.pass = a;
 }
 
 void rec_reduce(const double* partial, int G, int64_t elems, double* out,
@@ -183,27 +206,60 @@ __shared__ double g_pool_scr[kPoolScr];
 // Every body is its own (not inlined) function, so that each gets the
 // register allocation it would have as a kernel instead of sharing one
 // allocation with all the others.
+//
+// A body receives its step record as a function argument, which the
+// compiler must assume divergent and generic.  uniform_const makes the
+// record's address wave-uniform and constant-address-space (the records do
+// not change while the kernel runs), so its fields come from scalar loads
+// into scalar registers and the body's loop control stays scalar, as in
+// the lone kernels; the pointers in the record are generic, so the bodies
+// access global memory through gload / gstore (global instructions, which
+// the hardware does not count with the LDS operations).
+template <typename P>
+__device__ __forceinline__ const P* uniform_const(const P* p) {
+  const uint64_t v = (uint64_t)p;
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+  typedef const __attribute__((address_space(4))) P CP;
+  return (const P*)(CP*)(((uint64_t)hi << 32) | lo);
+}
 
-// pass bodies: four waves, two register-staged buffers, Gram pair slots for
-// the most pairs a wave can get
-template <int TR, int CAP, int NTB, bool GRAM>
+// pass bodies: four waves, two tile buffers filled by direct copies or,
+// where the lone launch staged through registers (columns not 16-byte
+// aligned), through registers (the same tile layout either way), Gram pair
+// slots for the most pairs a wave can get
+template <int TR, int CAP, int NTB, bool GRAM, bool REG>
 __device__ __noinline__ void pass_item(const p16::ArgsT<double>* a,
-                                       int64_t g, int64_t G) {
+                                       int64_t g0, int64_t g1, int64_t G) {
   constexpr int kTop = ((CAP / 16) * NTB + 3) / 4;
   constexpr int MAXP = kTop < 1 ? 1 : kTop;
   using K = p16::Kernel<double, TR, 2, CAP, 2, 4, false, MAXP, GRAM, NTB,
-                        true, 0>;
+                        REG, 0>;
   static_assert(TR * CAP <= kPoolTile, "tile fits the pool");
   static_assert(K::kScrElems <= kPoolScr, "partial sums fit the pool");
-  K::run_with(*a, g_pool_b0, g_pool_b1, nullptr, nullptr, g_pool_scr, g, G);
+  const p16::ArgsT<double>& b = *uniform_const(a);
+  for (int64_t g = g0; g < g1; ++g) {
+    if (g > g0) __syncthreads();     // the previous item's LDS reads are done
+    K::run_with(b, g_pool_b0, g_pool_b1, nullptr, nullptr, g_pool_scr, g, G);
+  }
 }
 
-template <int TR, int CAP>
+template <int TR, int CAP, bool REG>
 __device__ __forceinline__ void pass_tr(const p16::ArgsT<double>* a, int ntb,
-                                        int64_t g, int64_t G) {
-  if (ntb == 0) pass_item<TR, CAP, 1, false>(a, g, G);
-  else if (ntb == 1) pass_item<TR, CAP, 1, true>(a, g, G);
-  else pass_item<TR, CAP, 2, true>(a, g, G);
+                                        int64_t g0, int64_t g1, int64_t G) {
+  if (ntb == 0) pass_item<TR, CAP, 1, false, REG>(a, g0, g1, G);
+  else if (ntb == 1) pass_item<TR, CAP, 1, true, REG>(a, g0, g1, G);
+  else pass_item<TR, CAP, 2, true, REG>(a, g0, g1, G);
+}
+
+template <bool REG>
+__device__ __forceinline__ void pass_unit(const BatchStep* st, int sel,
+                                          int64_t g0, int64_t g1) {
+  const int code = sel / 3, ntb = sel % 3;
+  if (code == 0) pass_tr<16, 272, REG>(&st->u.pass, ntb, g0, g1, st->items);
+  else if (code == 1)
+    pass_tr<32, 128, REG>(&st->u.pass, ntb, g0, g1, st->items);
+  else pass_tr<64, 64, REG>(&st->u.pass, ntb, g0, g1, st->items);
 }
 
 template <int S>
@@ -212,16 +268,18 @@ __device__ __noinline__ void epi_item(const EpiArgs* a) {
   const EpiView sm{p, g_pool_b1, p + 256, p + 512, p + 768, p + 1024,
                    p + 1280, p + 1536, p + 1792, p + 2048, p + 2560,
                    reinterpret_cast<int*>(p + 2564)};
-  epilogue_all<S>(*a, sm);
+  epilogue_all<S>(*uniform_const(a), sm);
 }
 
 template <int S>
 __device__ __noinline__ void leaf_item(const LeafA* l, int64_t item) {
+  l = uniform_const(l);
   tw::leaf_body<double, S>(l->v, l->ldv, l->m, l->nchunks, l->rleaf, item);
 }
 
 template <int S>
 __device__ __noinline__ void node_item(const NodeA* n, int64_t item) {
+  n = uniform_const(n);
   tw::node_body<S>(n->rprev, n->nprev, n->fan, n->nnodes, n->rcur, n->qcur,
                    n->is_root, n->r_out, n->r_rs, n->r_cs, n->syncs,
                    g_pool_b0, item);
@@ -229,11 +287,13 @@ __device__ __noinline__ void node_item(const NodeA* n, int64_t item) {
 
 template <int S>
 __device__ __noinline__ void apply_item(const ApplyA* p, int64_t item) {
+  p = uniform_const(p);
   tw::apply_body<double, S>(p->v, p->ldv, p->m, p->nchunks, p->cleaf, p->dst,
                             p->ldd, g_pool_b0, item);
 }
 
 __device__ __noinline__ void small_item(const BatchStep* st, int64_t item) {
+  st = uniform_const(st);
   switch (st->kind) {
     case SK_INIT:
       info_init_body(st->u.init.info);
@@ -263,15 +323,8 @@ __device__ __forceinline__ void tsqr_item(const BatchStep* st, int64_t item) {
   else apply_item<S>(&st->u.apply, item);
 }
 
-__device__ __forceinline__ void run_item(const BatchStep* st, int64_t item) {
+__device__ __forceinline__ void run_one(const BatchStep* st, int64_t item) {
   switch (st->kind) {
-    case SK_PASS: {
-      const int code = st->sel / 3, ntb = st->sel % 3;
-      if (code == 0) pass_tr<16, 272>(&st->u.pass, ntb, item, st->items);
-      else if (code == 1) pass_tr<32, 128>(&st->u.pass, ntb, item, st->items);
-      else pass_tr<64, 64>(&st->u.pass, ntb, item, st->items);
-      break;
-    }
     case SK_EPI:
       if (st->sel == 4) epi_item<4>(&st->u.epi);
       else if (st->sel == 8) epi_item<8>(&st->u.epi);
@@ -289,49 +342,96 @@ __device__ __forceinline__ void run_item(const BatchStep* st, int64_t item) {
   }
 }
 
-__global__ void persist_reset(ProbCtl* ctl, int nprob, unsigned* flags) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < nprob) {
-    ctl[i].w = 0;
-    ctl[i].done = 0;
+// Unit `unit` of a step: its items [unit chunk, (unit + 1) chunk), one
+// after another (the same bodies with the same item indices as alone).
+__device__ __forceinline__ void run_unit(const BatchStep* st, int unit) {
+  const int64_t g0 = (int64_t)unit * st->chunk;
+  const int64_t g1 = min((int64_t)st->items, g0 + st->chunk);
+  if (st->kind == SK_PASS) {
+    if (st->sel >= 9) pass_unit<true>(st, st->sel - 9, g0, g1);
+    else pass_unit<false>(st, st->sel, g0, g1);
+    return;
   }
-  if (i == 0) {
-    flags[0] = 0;   // problems finished
-    flags[1] = 0;   // gave up
+  for (int64_t g = g0; g < g1; ++g) {
+    if (g > g0) __syncthreads();
+    run_one(st, g);
   }
 }
 
+__device__ __forceinline__ int units_of(const BatchStep* st) {
+  return (st->items + st->chunk - 1) / st->chunk;
+}
+
+// Identifier of the accelerator complex die (XCD) this wave runs on: its
+// L2 cache domain (hardware register XCC_ID, bits 3:0).
+__device__ __forceinline__ int xcc_id() {
+  return __builtin_amdgcn_s_getreg((3 << 11) | 20) & 15;
+}
+
+// flags: [0] problems finished, [1] gave up, [2 + x] problems adopted and
+// not finished by XCD x (x < 16)
+constexpr int kFlags = 18;
+
+__global__ void persist_reset(ProbCtl* ctl, int nprob, unsigned* flags) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nprob) {
+    ctl[i].w = kNoOwner;
+    ctl[i].done = 0;
+  }
+  if (i < kFlags) flags[i] = 0;
+}
+
 constexpr uint64_t kIdleTicks = 1000000000ull;   // 10 s at 100 MHz
+
+// Ordering between the units of a problem.  All of a problem's units run on
+// the XCD that adopted it, so they share that XCD's L2: a unit's stores
+// need only be complete in the L2 (s_waitcnt vmcnt(0)) before the unit is
+// counted done, with no write-back of the L2 to memory, which with
+// thousands of units per millisecond would keep every L2 writing.  A unit
+// that starts a new step invalidates its caches at agent scope (the L1 and
+// the non-coherent L2 lines; dirty lines stay): measured on MI355X,
+// invalidating the L1 alone left units reading stale data.
+__device__ __forceinline__ void unit_acquire() {
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+}
+__device__ __forceinline__ void unit_release() {
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+}
+
+template <typename W>
+__device__ __forceinline__ W ld_agent(W* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
 
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
 void persist_kernel(const BatchStep* __restrict__ steps,
                     const int* __restrict__ first,
                     const int* __restrict__ nsteps,
+                    const int* __restrict__ order,
                     bcgs_info* const* __restrict__ infos, int nprob,
-                    ProbCtl* ctl, unsigned* flags) {
+                    ProbCtl* ctl, unsigned* flags, int max_live) {
   __shared__ int sh[4];
   const int tid = threadIdx.x, lane = tid & 63;
+  const unsigned long long mine = (unsigned long long)xcc_id();
   int start = blockIdx.x % nprob;
+  int last_p = -1, last_s = -1;     // step of this workgroup's last unit
   uint64_t idle_since = wall_clock64();
   for (;;) {
-    // ---- wave 0 looks for a free item, 64 problems at a time ----
+    // ---- wave 0 looks for a free unit, 64 problems at a time ----
     if (tid < 64) {
       int fp = -1, fs = 0, fi = 0, ex = 0;
-      if (__hip_atomic_load(&flags[0], __ATOMIC_RELAXED,
-                            __HIP_MEMORY_SCOPE_AGENT) >= (unsigned)nprob ||
-          __hip_atomic_load(&flags[1], __ATOMIC_RELAXED,
-                            __HIP_MEMORY_SCOPE_AGENT) != 0)
+      if (ld_agent(&flags[0]) >= (unsigned)nprob || ld_agent(&flags[1]) != 0)
         ex = 1;
+      // 1. a unit of the current step of a problem this XCD owns
       for (int base = 0; !ex && fp < 0 && base < nprob; base += 64) {
         int p = start + base + lane;
         p = p >= nprob ? p - nprob : p;
         bool open = false;
         if (base + lane < nprob) {
-          const unsigned long long w = __hip_atomic_load(
-              &ctl[p].w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          const int s = (int)(w >> 32);
-          open = s < nsteps[p] &&
-                 (unsigned)w < (unsigned)steps[first[p] + s].items;
+          const unsigned long long w = ld_agent(&ctl[p].w);
+          const int st = (int)((w >> 32) & 0xFFFFFF);
+          open = (w >> 56) == mine && st < nsteps[p] &&
+                 (unsigned)w < (unsigned)units_of(&steps[first[p] + st]);
         }
         unsigned long long cand = __ballot(open);
         // claim from the candidates in order, one at a time
@@ -341,11 +441,11 @@ void persist_kernel(const BatchStep* __restrict__ steps,
           int got = 0, gs = 0, gi = 0;
           if (lane == k) {
             const unsigned long long w2 = __hip_atomic_fetch_add(
-                &ctl[p].w, 1ull, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-            gs = (int)(w2 >> 32);
+                &ctl[p].w, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            gs = (int)((w2 >> 32) & 0xFFFFFF);
             gi = (int)(unsigned)w2;
             got = gs < nsteps[p] &&
-                  (unsigned)gi < (unsigned)steps[first[p] + gs].items;
+                  gi < units_of(&steps[first[p] + gs]);
           }
           got = __shfl(got, k);
           if (got) {
@@ -355,6 +455,50 @@ void persist_kernel(const BatchStep* __restrict__ steps,
           }
         }
       }
+      // 2. adopt the largest problem nobody owns yet (claiming
+      //    unit 0 of its first step with the same exchange), if this XCD
+      //    runs fewer than max_live problems: a slot is reserved first
+      //    (and returned when nothing is adopted), so the limit is exact
+      //    and problems are handed out as XCDs make room, largest first
+      bool slot = false;
+      if (!ex && fp < 0 && lane == 0 &&
+          ld_agent(&flags[2 + mine]) < (unsigned)max_live) {
+        const unsigned had = __hip_atomic_fetch_add(
+            &flags[2 + mine], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        slot = had < (unsigned)max_live;
+        if (!slot)
+          __hip_atomic_fetch_sub(&flags[2 + mine], 1u, __ATOMIC_RELAXED,
+                                 __HIP_MEMORY_SCOPE_AGENT);
+      }
+      slot = __shfl((int)slot, 0) != 0;
+      if (slot) {
+        for (int base = 0; fp < 0 && base < nprob; base += 64) {
+          const int j = base + lane;
+          const int p = j < nprob ? order[j] : 0;
+          const bool free_p = j < nprob && ld_agent(&ctl[p].w) == kNoOwner;
+          unsigned long long cand = __ballot(free_p);
+          while (cand && fp < 0) {
+            const int k = __ffsll((long long)cand) - 1;
+            cand &= cand - 1;
+            int got = 0;
+            if (lane == k) {
+              unsigned long long expect = kNoOwner;
+              got = __hip_atomic_compare_exchange_strong(
+                  &ctl[p].w, &expect, (mine << 56) | 1ull, __ATOMIC_RELAXED,
+                  __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+            got = __shfl(got, k);
+            if (got) {
+              fp = __shfl(p, k);
+              fs = 0;
+              fi = 0;
+            }
+          }
+        }
+        if (fp < 0 && lane == 0)       // nothing left to adopt
+          __hip_atomic_fetch_sub(&flags[2 + mine], 1u, __ATOMIC_RELAXED,
+                                 __HIP_MEMORY_SCOPE_AGENT);
+      }
       if (lane == 0) {
         sh[0] = fp;
         sh[1] = fs;
@@ -363,7 +507,10 @@ void persist_kernel(const BatchStep* __restrict__ steps,
       }
     }
     __syncthreads();
-    const int p = sh[0], s = sh[1], it = sh[2], ex = sh[3];
+    const int p = __builtin_amdgcn_readfirstlane(sh[0]);
+    const int s = __builtin_amdgcn_readfirstlane(sh[1]);
+    const int it = __builtin_amdgcn_readfirstlane(sh[2]);
+    const int ex = __builtin_amdgcn_readfirstlane(sh[3]);
     __syncthreads();
     if (ex) break;
     if (p < 0) {
@@ -373,9 +520,9 @@ void persist_kernel(const BatchStep* __restrict__ steps,
           __hip_atomic_store(&flags[1], 1u, __ATOMIC_RELAXED,
                              __HIP_MEMORY_SCOPE_AGENT);
           for (int q = 0; q < nprob; ++q) {
-            const unsigned long long w = __hip_atomic_load(
-                &ctl[q].w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            if ((int)(w >> 32) < nsteps[q]) infos[q]->status = BCGS_ERR_HIP;
+            const unsigned long long w = ld_agent(&ctl[q].w);
+            if ((int)((w >> 32) & 0xFFFFFF) < nsteps[q])
+              infos[q]->status = BCGS_ERR_HIP;
           }
         }
         break;
@@ -384,24 +531,32 @@ void persist_kernel(const BatchStep* __restrict__ steps,
       continue;
     }
     idle_since = wall_clock64();
-    // ---- the item, after everything the earlier steps wrote ----
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    const BatchStep& st = steps[first[p] + s];
-    run_item(&st, it);
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    // ---- the unit, after everything the earlier steps wrote (already
+    //      acquired when this workgroup's last unit was of the same step) ----
+    if (p != last_p || s != last_s) unit_acquire();
+    last_p = p;
+    last_s = s;
+    const BatchStep* st = &steps[first[p] + s];
+    run_unit(st, it);
+    unit_release();
     __syncthreads();
     if (tid == 0) {
       const unsigned d = __hip_atomic_fetch_add(
-          &ctl[p].done, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-      if (d + 1 == (unsigned)st.items) {
+          &ctl[p].done, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (d + 1 == (unsigned)units_of(st)) {
         // the step is complete: open the next one
         __hip_atomic_store(&ctl[p].done, 0u, __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_store(&ctl[p].w, (unsigned long long)(s + 1) << 32,
-                           __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        if (s + 1 == nsteps[p])
-          __hip_atomic_fetch_add(&flags[0], 1u, __ATOMIC_RELEASE,
+        unit_release();         // the reset lands before the step opens
+        __hip_atomic_store(&ctl[p].w,
+                           (mine << 56) | ((unsigned long long)(s + 1) << 32),
+                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (s + 1 == nsteps[p]) {
+          __hip_atomic_fetch_add(&flags[0], 1u, __ATOMIC_RELAXED,
                                  __HIP_MEMORY_SCOPE_AGENT);
+          __hip_atomic_fetch_sub(&flags[2 + mine], 1u, __ATOMIC_RELAXED,
+                                 __HIP_MEMORY_SCOPE_AGENT);
+        }
       }
     }
     start = p;
@@ -417,6 +572,7 @@ struct PersistState {
   int* d_nsteps = nullptr;
   bcgs_info** d_infos = nullptr;
   ProbCtl* d_ctl = nullptr;
+  int* d_order = nullptr;
   unsigned* d_flags = nullptr;
   int nprob = 0;
   size_t nstep_total = 0;
@@ -433,6 +589,7 @@ void free_state(PersistState& s) {
   (void)hipFree(s.d_nsteps);
   (void)hipFree(s.d_infos);
   (void)hipFree(s.d_ctl);
+  (void)hipFree(s.d_order);
   (void)hipFree(s.d_flags);
   const hipStream_t gs = s.graph_stream;   // kept for the next batch
   s = PersistState{};
@@ -469,8 +626,12 @@ bcgs_status persist_launch(const std::vector<char>& key,
                            const std::vector<BatchStep>& steps,
                            const std::vector<int>& first,
                            const std::vector<int>& nsteps,
+                           const std::vector<int>& order,
                            const bcgs_problem* probs, int count,
                            hipStream_t stream) {
+  // problems an XCD runs at a time: measured 4 to 6 best on the batched
+  // workload (more and the XCDs finish unevenly, fewer and they idle)
+  constexpr int max_live = 6;
   std::lock_guard<std::mutex> lock(g_pmu);
   PersistState& s = g_persist[stream];
   if (s.key != key || !s.exec) {
@@ -485,7 +646,8 @@ bcgs_status persist_launch(const std::vector<char>& key,
         hipMalloc(&s.d_nsteps, count * sizeof(int)) != hipSuccess ||
         hipMalloc(&s.d_infos, count * sizeof(bcgs_info*)) != hipSuccess ||
         hipMalloc(&s.d_ctl, count * sizeof(ProbCtl)) != hipSuccess ||
-        hipMalloc(&s.d_flags, 2 * sizeof(unsigned)) != hipSuccess) {
+        hipMalloc(&s.d_order, count * sizeof(int)) != hipSuccess ||
+        hipMalloc(&s.d_flags, kFlags * sizeof(unsigned)) != hipSuccess) {
       free_state(s);
       return BCGS_ERR_NOMEM;
     }
@@ -496,6 +658,8 @@ bcgs_status persist_launch(const std::vector<char>& key,
         hipMemcpy(s.d_nsteps, nsteps.data(), count * sizeof(int),
                   hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(s.d_infos, infos.data(), count * sizeof(bcgs_info*),
+                  hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(s.d_order, order.data(), count * sizeof(int),
                   hipMemcpyHostToDevice) != hipSuccess) {
       free_state(s);
       return BCGS_ERR_HIP;
@@ -515,12 +679,14 @@ bcgs_status persist_launch(const std::vector<char>& key,
     if (hipStreamBeginCapture(s.graph_stream, hipStreamCaptureModeRelaxed) !=
         hipSuccess)
       return BCGS_ERR_HIP;
-    hipLaunchKernelGGL(persist_reset, dim3((unsigned)cdiv(count, 256)),
+    hipLaunchKernelGGL(persist_reset,
+                       dim3((unsigned)cdiv(std::max(count, kFlags), 256)),
                        dim3(256), 0, s.graph_stream, s.d_ctl, count,
                        s.d_flags);
     hipLaunchKernelGGL(persist_kernel, dim3((unsigned)(2 * cus)), dim3(256),
                        0, s.graph_stream, s.d_steps, s.d_first, s.d_nsteps,
-                       s.d_infos, count, s.d_ctl, s.d_flags);
+                       s.d_order, s.d_infos, count, s.d_ctl, s.d_flags,
+                       max_live);
     hipGraph_t graph = nullptr;
     if (hipStreamEndCapture(s.graph_stream, &graph) != hipSuccess || !graph)
       return BCGS_ERR_HIP;
@@ -564,7 +730,17 @@ bcgs_status persist_run(const std::vector<Plan>& plans,
                       &first, &nsteps))
     return BCGS_OK;
   *used = true;
-  return persist_launch(key, steps, first, nsteps, probs, count, stream);
+  // adoption order: largest modelled work first (streamed m x n x q)
+  std::vector<int> order(count);
+  for (int i = 0; i < count; ++i) order[i] = i;
+  auto work = [&](int i) {
+    return (double)probs[i].m * (double)probs[i].n *
+           (double)(probs[i].n / probs[i].s);
+  };
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int a, int b) { return work(a) > work(b); });
+  return persist_launch(key, steps, first, nsteps, order, probs, count,
+                        stream);
 }
 
 void persist_release() {

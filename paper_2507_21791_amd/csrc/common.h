@@ -24,6 +24,21 @@ constexpr int kMaxS = 64;          // largest block width
 constexpr int kThreads = 256;      // threads per workgroup of every kernel
 constexpr int kWaves = kThreads / 64;
 
+// Global-memory access through an explicit global-address-space pointer.
+// Kernels see their pointer arguments as global already; a device function
+// that receives its pointers from memory (a step record of the persistent
+// batch) would otherwise use flat instructions, which the hardware counts
+// together with LDS operations, so every LDS wait would also wait for the
+// global loads in flight.
+template <typename T>
+__device__ __forceinline__ T gload(const T* p) {
+  return *(const __attribute__((address_space(1))) T*)p;
+}
+template <typename T>
+__device__ __forceinline__ void gstore(T* p, T v) {
+  *(__attribute__((address_space(1))) T*)p = v;
+}
+
 inline int round_up(int x, int m) { return (x + m - 1) / m * m; }
 inline int64_t round_up64(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }

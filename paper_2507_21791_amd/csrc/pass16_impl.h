@@ -146,7 +146,7 @@ __device__ void tile_sync(const ArgsT<T>& a, T* buf, int64_t r0, int rows) {
     if (r < rows) {
       int64_t ld;
       const T* src = col_ptr(a, c, &ld);
-      v = src[r0 + r];
+      v = gload(src + r0 + r);
     }
     buf[at<T, TR>(c, r)] = v;
   }
@@ -181,7 +181,7 @@ __device__ __forceinline__ void combine(const ArgsT<T>& a, T* tile,
 #pragma unroll
     for (int k = 0; k < KG; ++k) sum += part[k];
     tile[at<T, TR>(uc0 + c, r)] = sum;
-    if (r < rows) dst[(int64_t)c * ldd + r0 + r] = sum;
+    if (r < rows) gstore(dst + (int64_t)c * ldd + r0 + r, sum);
   }
 }
 
@@ -299,13 +299,13 @@ struct Kernel {
     for (int i = 0; i < IPW; ++i) {
       const T* p = copy_src(a, S, i, r0);
       if constexpr (E == 2) {
-        pend[i].x = p[0];
-        pend[i].y = p[1];
+        pend[i].x = gload(p);
+        pend[i].y = gload(p + 1);
       } else {
-        pend[i].x = p[0];
-        pend[i].y = p[1];
-        pend[i].z = p[2];
-        pend[i].w = p[3];
+        pend[i].x = gload(p);
+        pend[i].y = gload(p + 1);
+        pend[i].z = gload(p + 2);
+        pend[i].w = gload(p + 3);
       }
     }
   }
@@ -614,14 +614,17 @@ struct Kernel {
     for (int i = 0; i < KF; ++i) {
       const int k = S.kb + i;
       const int row = 4 * k + lk;
-      S.c1f[i] = (k < S.ke && k < nks1) ? (T)a.c1[row * 16 + li] : T(0);
-      S.c2f[i] = (k < S.ke && k < S.nks2) ? (T)a.c2[row * 16 + li] : T(0);
+      S.c1f[i] = (k < S.ke && k < nks1) ? (T)gload(a.c1 + row * 16 + li)
+                                        : T(0);
+      S.c2f[i] = (k < S.ke && k < S.nks2) ? (T)gload(a.c2 + row * 16 + li)
+                                           : T(0);
     }
 #pragma unroll
     for (int u = 0; u < kTail; ++u) {
       const int t = S.kg + KG * u;
       S.c2o[u] = (a.upd2 && t < S.sq)
-                     ? (T)a.c2[(4 * (S.nks2 + t) + lk) * 16 + li] : T(0);
+                     ? (T)gload(a.c2 + (4 * (S.nks2 + t) + lk) * 16 + li)
+                     : T(0);
     }
     // ---- Gram pairs p = wave + NW i, p = (A block) * NTB + (B block) ----
     const int nta = a.ga_p >> 4;
@@ -704,15 +707,16 @@ struct Kernel {
           // acc[i][v] at lane l: A column ta + 4 lk + v, B column b*16 + li
 #pragma unroll
           for (int v = 0; v < 4; ++v)
-            out[(size_t)(b * 16 + li) * a.ga_p + ta + 4 * lk + v] =
-                (double)S.acc[i][v];
+            gstore(out + (size_t)(b * 16 + li) * a.ga_p + ta + 4 * lk + v,
+                   (double)S.acc[i][v]);
         } else {
           // acc[i][q] at lane l: A column ta + 4 ((l >> 2) & 3) + lk,
           // B column b * 16 + 4 (l & 3) + q
 #pragma unroll
           for (int q = 0; q < 4; ++q)
-            out[(size_t)(b * 16 + 4 * (lane & 3) + q) * a.ga_p + ta +
-                4 * ((lane >> 2) & 3) + lk] = S.acc[i][q];
+            gstore(out + (size_t)(b * 16 + 4 * (lane & 3) + q) * a.ga_p +
+                       ta + 4 * ((lane >> 2) & 3) + lk,
+                   S.acc[i][q]);
         }
       }
     }
@@ -745,8 +749,9 @@ void pass16_deep_kernel(ArgsT<T> a) {
 }
 
 // recording of a pass (batch_persist.hip): tile rows, waves, B blocks of
-// the Gram (0: none), workgroups
-void rec_pass16(const ArgsT<double>& a, int tr, int nw, int gram_ntb, int G);
+// the Gram (0: none), workgroups, tiles staged through registers
+void rec_pass16(const ArgsT<double>& a, int tr, int nw, int gram_ntb, int G,
+                bool reg);
 
 template <typename T, int TR, int NBUF, int CAP, int PC, int NW, bool SCR2,
           int MAXP, bool GRAM, int NTB, bool REG, int KS = 0>
@@ -763,7 +768,7 @@ static hipError_t go(const ArgsT<T>& a, int G, hipStream_t st, int* tag) {
     // the same pass as a step of G work items: any shape with four waves
     // per workgroup (K split four ways, as here) gives the same bits
     if constexpr (sizeof(T) == 8 && NW == 4)
-      rec_pass16(a, TR, NW, GRAM ? NTB : 0, G);
+      rec_pass16(a, TR, NW, GRAM ? NTB : 0, G, REG);
     else
       rec_unsupported();
     return hipSuccess;
