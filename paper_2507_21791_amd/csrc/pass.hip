@@ -109,28 +109,35 @@ __device__ void update_partials(const PassArgs<T>& a, const T* tile,
       }
     };
     if constexpr (MULTI) {
-      // four independent MFMA chains, the operand loads of a group issued
-      // together, summed in a fixed order at the end
+      // four independent MFMA chains over groups of 16 K-steps: the 16
+      // coefficient loads (global) and tile loads of a group are issued
+      // before its first MFMA; the chains are summed in a fixed order
       typename Mma<T>::acc acc1 = acc, acc2 = acc, acc3 = acc;
-      for (int kk = kb; kk < ke; kk += 4) {
-        T a0, b0, a1, b1, a2, b2, a3, b3;
-        operands(kk, a0, b0);
-        operands(kk + 1, a1, b1);
-        operands(kk + 2, a2, b2);
-        operands(kk + 3, a3, b3);
-        acc = Mma<T>::mac(a0, b0, acc);
-        acc1 = Mma<T>::mac(a1, b1, acc1);
-        acc2 = Mma<T>::mac(a2, b2, acc2);
-        acc3 = Mma<T>::mac(a3, b3, acc3);
+      constexpr int kG = 16;
+      for (int kk = kb; kk < ke; kk += kG) {
+        T av[kG], bv[kG];
+#pragma unroll
+        for (int u = 0; u < kG; ++u) operands(kk + u, av[u], bv[u]);
+#pragma unroll
+        for (int u = 0; u < kG; u += 4) {
+          acc = Mma<T>::mac(av[u], bv[u], acc);
+          acc1 = Mma<T>::mac(av[u + 1], bv[u + 1], acc1);
+          acc2 = Mma<T>::mac(av[u + 2], bv[u + 2], acc2);
+          acc3 = Mma<T>::mac(av[u + 3], bv[u + 3], acc3);
+        }
       }
       acc += acc1;
       acc2 += acc3;
       acc += acc2;
     } else {
-      for (int kk = kb; kk < ke; ++kk) {
-        T av, bv;
-        operands(kk, av, bv);
-        acc = Mma<T>::mac(av, bv, acc);
+      // one chain (the Gram accumulators hold the registers); the loads of
+      // four K-steps are issued before their MFMAs
+      for (int kk = kb; kk < ke; kk += 4) {
+        T av[4], bv[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) operands(kk + u, av[u], bv[u]);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) acc = Mma<T>::mac(av[u], bv[u], acc);
       }
     }
     T* out = scr + (size_t)ks * tr * srow;
@@ -187,16 +194,29 @@ __global__ __launch_bounds__(kThreads) void pass_kernel(PassArgs<T> a) {
   const int nstage = a.ncols_p << tr_shift;
   for (int64_t r0 = row_begin; r0 < row_end; r0 += tr) {
     const int rows = (int)min((int64_t)tr, row_end - r0);
-    // 1. stage the column window (zero past m and past ncols)
-    for (int idx = tid; idx < nstage; idx += kThreads) {
-      const int c = idx >> tr_shift, r = idx & (tr - 1);
-      T v = 0;
-      if (r < rows && c < a.ncols) {
-        int64_t ld;
-        const T* src = col_src(a, c, &ld);
-        v = src[r0 + r];
+    // 1. stage the column window (zero past m and past ncols), eight
+    //    elements per thread at a time: all eight loads are issued before
+    //    the first is written to LDS
+    constexpr int kBatch = 8;
+    for (int base = tid; base < nstage; base += kBatch * kThreads) {
+      T v[kBatch];
+#pragma unroll
+      for (int u = 0; u < kBatch; ++u) {
+        const int idx = base + u * kThreads;
+        const int c = idx >> tr_shift, r = idx & (tr - 1);
+        v[u] = 0;
+        if (idx < nstage && r < rows && c < a.ncols) {
+          int64_t ld;
+          const T* src = col_src(a, c, &ld);
+          v[u] = src[r0 + r];
+        }
       }
-      tile[c * trp + r] = v;
+#pragma unroll
+      for (int u = 0; u < kBatch; ++u) {
+        const int idx = base + u * kThreads;
+        if (idx < nstage)
+          tile[(idx >> tr_shift) * trp + (idx & (tr - 1))] = v[u];
+      }
     }
     __syncthreads();
     // 2-3. block updates, both on the staged columns
