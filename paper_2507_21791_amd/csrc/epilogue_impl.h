@@ -164,6 +164,48 @@ __device__ __forceinline__ double gram_at(const EpiArgs& a, int r, int c) {
   return a.gram[(size_t)c * a.gld + r];
 }
 
+// out(x, y) = sum_{r < js} G(r, ca + x) G(r, cb + y) for x, y < s (s a
+// multiple of 16; out row-major with stride s, in LDS) on the FP64
+// 16x16x4 MFMA: the 16 x 16 output tiles go round-robin to the waves, each
+// running over all js rows (K = 4 rows per step; the Gram rows are read
+// from global memory, where they are L2 resident).
+__device__ void gram_mfma(const EpiArgs& a, int js, int ca, int cb, int s,
+                          double* out) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int nb = s >> 4, ntile = nb * nb;
+  constexpr int kT = (kMaxS / 16) * (kMaxS / 16) / kWaves;
+  v4d acc[kT];
+#pragma unroll
+  for (int i = 0; i < kT; ++i) acc[i] = v4d{0.0, 0.0, 0.0, 0.0};
+  const int nsteps = (js + 3) >> 2;
+  for (int t = 0; t < nsteps; ++t) {
+    const int r = 4 * t + lk;
+#pragma unroll
+    for (int i = 0; i < kT; ++i) {
+      const int id = wave + kWaves * i;
+      if (id < ntile) {
+        const int bx = id / nb, by = id % nb;
+        const double x = r < js ? gram_at(a, r, ca + 16 * bx + li) : 0.0;
+        const double y = r < js ? gram_at(a, r, cb + 16 * by + li) : 0.0;
+        acc[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(x, y, acc[i], 0, 0, 0);
+      }
+    }
+  }
+  // acc[i][v] at lane l: output row 16 bx + l / 16 + 4 v, column 16 by + l % 16
+#pragma unroll
+  for (int i = 0; i < kT; ++i) {
+    const int id = wave + kWaves * i;
+    if (id < ntile) {
+      const int bx = id / nb, by = id % nb;
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        out[(16 * bx + lk + 4 * v) * s + 16 * by + li] = acc[i][v];
+    }
+  }
+  __syncthreads();
+}
+
 // Tall-by-small products on the FP64 16x16x4 MFMA, for block widths
 // S = 4, 8, 16: out(i, c, v) receives v = sum_{k < S} A(i, k) P(k, c) for
 // i < rows and c < 16, with P a 16 x 16 row-major LDS matrix that is zero
@@ -594,6 +636,10 @@ __device__ bool epilogue_body(EpiArgs a, const EpiView& sm) {
       double ss = 0.0, unused1 = 0.0, unused2 = 0.0;
       gram_products<S>(a, js, false, sm.B, ss, unused1, unused2);
       if (tid < S * S) sm.A[tid] = gram_at(a, js + tid / S, tid % S) - ss;
+    } else if (s % 16 == 0) {
+      gram_mfma(a, js, 0, 0, s, sm.B);
+      for (int e = tid; e < s * s; e += kThreads)
+        sm.A[e] = gram_at(a, js + e / s, e % s) - sm.B[e];
     } else {
       for (int e = tid; e < s * s; e += kThreads) {
         const int x = e / s, y = e % s;
@@ -622,6 +668,17 @@ __device__ bool epilogue_body(EpiArgs a, const EpiView& sm) {
   for (int t = 0; t < kPer; ++t) yy[t] = yz[t] = zz[t] = 0.0;
   if constexpr (S == 4 || S == 8 || S == 16) {
     gram_products<S>(a, js, a.has_e, sm.B, yy[0], yz[0], zz[0]);
+  } else if (s % 16 == 0) {
+    // the three products one after another through sm.A
+    for (int p = 0; p < (a.has_e ? 3 : 1); ++p) {
+      gram_mfma(a, js, p == 2 ? s : 0, p == 0 ? 0 : s, s, sm.A);
+#pragma unroll
+      for (int t = 0; t < kPer; ++t) {
+        const int e = tid + t * kThreads;
+        if (e < s * s) (p == 0 ? yy : p == 1 ? yz : zz)[t] = sm.A[e];
+      }
+      __syncthreads();
+    }
   } else {
     double* stg = sm.A;               // rows x w2, row-major
     const int crows = (kMaxS * kMaxS) / w2;
