@@ -100,6 +100,9 @@ struct TsqrPlan {
   int64_t r_off[24];         // offset (doubles) of level-l R factors
   int64_t q_off[24];         // offset of level-l node Q factors (l >= 1)
   int64_t c_off[24];         // offset of level-l downward coefficients
+  int64_t cnt_off;           // offset of the node arrival counters (ints,
+                             // one per node of levels 1..levels)
+  int64_t cnt_doubles;       // their size in doubles
   int64_t total;             // doubles
 };
 

@@ -259,6 +259,12 @@ struct Run {
     } else {
       hipLaunchKernelGGL(info_init_kernel, dim3(1), dim3(64), 0, st, info);
       check(hipGetLastError());
+      // the one-wave TSQR's node counters start at zero (each TSQR leaves
+      // them at zero again)
+      if (p.tsqr.wave)
+        check(launch_fill(dws(p.off_tsqr) + p.tsqr.cnt_off,
+                          p.tsqr.cnt_doubles, 1, p.tsqr.cnt_doubles, 0.0,
+                          st));
     }
     // [Q_0, R_00] = TSQR(X_0)
     tsqr(xb(0), ldx, qb(0), R, 1, ldr);

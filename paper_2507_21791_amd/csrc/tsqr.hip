@@ -368,6 +368,11 @@ TsqrPlan make_tsqr_plan(int64_t m, int s) {
     if (i >= 1) { p.q_off[i] = off; off += p.nodes[i] * (int64_t)p.fan * s * s; }
     else p.q_off[i] = -1;
   }
+  int64_t ncnt = 0;
+  for (int i = 1; i <= p.levels; ++i) ncnt += p.nodes[i];
+  p.cnt_off = off;
+  p.cnt_doubles = (ncnt + 1) / 2;
+  off += p.cnt_doubles;
   p.total = off;
   return p;
 }

@@ -56,26 +56,26 @@ static hipError_t launch_wave_tsqr_s(const TsqrPlan& tp, const T* v,
     }
     return hipSuccess;
   }
+  // three launches: the leaves, the whole upward tree, then the explicit
+  // Q with each chunk's coefficients formed along its path
   prof_begin(BCGS_KERNEL_TSQR_LEAF, 0, esz * m * S, 2.0 * m * ss);
   hipLaunchKernelGGL((tw::leaf_kernel<T, S>), wgs(tp.nchunks), dim3(256), 0,
                      st, v, ldv, m, tp.nchunks, ws + tp.r_off[0]);
   prof_name("tsqr_wave_leaf_kernel<%s, %d>", type_name<T>(), S);
   prof_end();
-  for (int l = 1; l <= tp.levels; ++l) {
-    const double rows = (double)tp.nodes[l - 1] * S;
-    prof_begin(BCGS_KERNEL_TSQR_NODE, l, 8.0 * rows * S * 2, 4.0 * rows * ss);
-    hipLaunchKernelGGL(tw::node_kernel<S>, wgs(tp.nodes[l]), dim3(256), 0, st,
-                       ws + tp.r_off[l - 1], tp.nodes[l - 1], fan,
-                       tp.nodes[l], ws + tp.r_off[l], ws + tp.q_off[l],
-                       l == tp.levels ? 1 : 0, r_out, r_rs, r_cs, syncs);
-    prof_name("tsqr_wave_node_kernel<%d>", S);
-    prof_end();
-  }
-  tsqr_down(tp, ws, st);
-  prof_begin(BCGS_KERNEL_TSQR_APPLY, 0, 2.0 * esz * m * S, 2.0 * m * ss);
-  hipLaunchKernelGGL((tw::apply_kernel<T, S>), wgs(tp.nchunks), dim3(256), 0,
-                     st, v, ldv, m, tp.nchunks, ws + tp.c_off[0], dst, ldd);
-  prof_name("tsqr_wave_apply_kernel<%s, %d>", type_name<T>(), S);
+  double tree_rows = 0.0;
+  for (int l = 1; l <= tp.levels; ++l) tree_rows += (double)tp.nodes[l - 1] * S;
+  prof_begin(BCGS_KERNEL_TSQR_NODE, 0, 16.0 * tree_rows * S,
+             4.0 * tree_rows * ss);
+  hipLaunchKernelGGL(tw::tree_kernel<S>, wgs(tp.nodes[1]), dim3(256), 0, st,
+                     tp, ws, r_out, r_rs, r_cs, syncs);
+  prof_name("tsqr_wave_tree_kernel<%d>", S);
+  prof_end();
+  prof_begin(BCGS_KERNEL_TSQR_APPLY, 0, 2.0 * esz * m * S,
+             2.0 * m * ss + 2.0 * (double)tp.nchunks * tp.levels * ss * S);
+  hipLaunchKernelGGL((tw::apply_path_kernel<T, S>), wgs(tp.nchunks),
+                     dim3(256), 0, st, v, ldv, m, tp, ws, dst, ldd);
+  prof_name("tsqr_wave_apply_path_kernel<%s, %d>", type_name<T>(), S);
   prof_end();
   return hipGetLastError();
 }

@@ -1,12 +1,21 @@
 // Device code of the s <= 16 TSQR (one wave per row chunk): included by
-// tsqr_wave.hip (its kernels) and by the batched persistent kernel, which
-// runs the same bodies as work items.
+// tsqr_wave.hip (its three kernels: leaves, the upward tree, the explicit
+// Q) and by the batched persistent kernel, which runs the leaf,
+// node, downward and apply bodies as steps of work items (the same
+// arithmetic in the same order, so the same bits).
 #pragma once
 
 #include "common.h"
 
 namespace bcgs {
 namespace tw {
+
+// Store of an R factor that a workgroup on another XCD may read in the
+// same launch (the one-launch tree): written through to the device level
+// (agent scope), so the writer need not write its whole L2 back.
+__device__ __forceinline__ void st_r(double* p, double v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
 
 template <int S>
 struct Geo {
@@ -265,7 +274,8 @@ __device__ __forceinline__ void leaf_body(
   if (lane < S) {
     double* out = rleaf + (size_t)chunk * S * S;
 #pragma unroll
-    for (int c = 0; c < S; ++c) out[c * S + lane] = c >= lane ? a[0][c] : 0.0;
+    for (int c = 0; c < S; ++c)
+      st_r(out + c * S + lane, c >= lane ? a[0][c] : 0.0);
   }
 }
 
@@ -274,14 +284,11 @@ __device__ __forceinline__ void leaf_body(
 // signs (R <- D R, Q <- Q D) and also writes R to r_out.  lds: 4 * 4 S^2
 // doubles of workgroup memory (one slice per wave).
 template <int S>
-__device__ __forceinline__ void node_body(
-    const double* __restrict__ rprev, int64_t nprev, int fan, int64_t nnodes,
+__device__ __forceinline__ void node_wave(
+    const double* __restrict__ rprev, int64_t nprev, int fan, int64_t node,
     double* __restrict__ rcur, double* __restrict__ qcur, int is_root,
-    double* r_out, int64_t r_rs, int64_t r_cs, int32_t* syncs, double* lds,
-    int64_t block) {
-  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int64_t node = block * 4 + wv;
-  if (node >= nnodes) return;
+    double* r_out, int64_t r_rs, int64_t r_cs, int32_t* syncs, double* my) {
+  const int lane = threadIdx.x & 63;
   // the root completes the synchronization point of this TSQR
   if (is_root && syncs != nullptr && lane == 0) *syncs += 1;
   constexpr int R = Geo<S>::R;
@@ -299,7 +306,6 @@ __device__ __forceinline__ void node_body(
                     ? rprev[(size_t)(c0 + ch) * S * S + (size_t)c * S + rr]
                     : 0.0;
   }
-  double* my = lds + wv * 4 * S * S;
   factor<S>(a, tau, my);
   double sgn[S];
 #pragma unroll
@@ -313,7 +319,7 @@ __device__ __forceinline__ void node_body(
 #pragma unroll
     for (int c = 0; c < S; ++c) {
       const double val = (c >= lane ? a[0][c] : 0.0) * mine;
-      rn[c * S + lane] = val;
+      st_r(rn + c * S + lane, val);
       if (is_root) r_out[lane * r_rs + c * r_cs] = val;
     }
   }
@@ -327,27 +333,96 @@ __device__ __forceinline__ void node_body(
   });
 }
 
+// one node per wave: workgroup `block` of 256 threads takes nodes
+// 4 block .. 4 block + 3
+template <int S>
+__device__ __forceinline__ void node_body(
+    const double* __restrict__ rprev, int64_t nprev, int fan, int64_t nnodes,
+    double* __restrict__ rcur, double* __restrict__ qcur, int is_root,
+    double* r_out, int64_t r_rs, int64_t r_cs, int32_t* syncs, double* lds,
+    int64_t block) {
+  const int wv = threadIdx.x >> 6;
+  const int64_t node = block * 4 + wv;
+  if (node >= nnodes) return;
+  node_wave<S>(rprev, nprev, fan, node, rcur, qcur, is_root, r_out, r_rs,
+               r_cs, syncs, lds + wv * 4 * S * S);
+}
+
 // apply pass: explicit Q rows of every chunk, optionally in place (lds as
 // for node_body)
+template <typename T, int S>
+__device__ __forceinline__ void apply_wave(
+    const T* v, int64_t ldv, int64_t m, int64_t chunk,
+    const double* __restrict__ cchunk, T* dst, int64_t ldd, double* my) {
+  const int lane = threadIdx.x & 63;
+  constexpr int R = Geo<S>::R;
+  const int64_t row0 = chunk * Geo<S>::L;
+  double a[R][S], tau[S];
+  load_chunk<T, S>(v, ldv, m, row0, a);
+  factor<S>(a, tau, my);
+  form_q<S>(a, cchunk, my,
+            [&](int k, int c, double q) {
+              const int64_t row = row0 + lane + 64 * k;
+              if (row < m) dst[(int64_t)c * ldd + row] = static_cast<T>(q);
+            });
+}
+
 template <typename T, int S>
 __device__ __forceinline__ void apply_body(
     const T* v, int64_t ldv, int64_t m, int64_t nchunks,
     const double* __restrict__ cleaf, T* dst, int64_t ldd, double* lds,
     int64_t block) {
-  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int wv = threadIdx.x >> 6;
   const int64_t chunk = block * 4 + wv;
   if (chunk >= nchunks) return;
-  constexpr int R = Geo<S>::R;
-  const int64_t row0 = chunk * Geo<S>::L;
-  double a[R][S], tau[S];
-  load_chunk<T, S>(v, ldv, m, row0, a);
-  double* my = lds + wv * 4 * S * S;
-  factor<S>(a, tau, my);
-  form_q<S>(a, cleaf + (size_t)chunk * S * S, my,
-            [&](int k, int c, double q) {
-              const int64_t row = row0 + lane + 64 * k;
-              if (row < m) dst[(int64_t)c * ldd + row] = static_cast<T>(q);
-            });
+  apply_wave<T, S>(v, ldv, m, chunk, cleaf + (size_t)chunk * S * S, dst, ldd,
+                   lds + wv * 4 * S * S);
+}
+
+// Coefficient block of leaf chunk `chunk` (S x S, column-major, into the
+// wave's LDS slice out): the downward pass restricted to the chunk's path
+// from the root, the same products in the same order as the per-level
+// down kernels (C_child = Q_parent[child block] C_parent, the root's
+// children taking their Q block).
+template <int S>
+__device__ __forceinline__ void path_coef(const TsqrPlan& tp,
+                                          const double* ws, int64_t chunk,
+                                          double* out) {
+  const int lane = threadIdx.x & 63;
+  const int L = tp.levels, fan = tp.fan, rows = fan * S;
+  int64_t anc[24];
+  anc[0] = chunk;
+  for (int l = 1; l <= L; ++l) anc[l] = anc[l - 1] / fan;
+  constexpr int kPer = (S * S + 63) / 64;
+  {
+    const double* qb = ws + tp.q_off[L] + (size_t)(anc[L - 1] % fan) * S;
+#pragma unroll
+    for (int t = 0; t < kPer; ++t) {
+      const int e = lane + 64 * t;
+      if (e < S * S) out[e] = qb[(size_t)(e / S) * rows + e % S];
+    }
+  }
+  for (int l = L - 1; l >= 1; --l) {
+    const double* qb = ws + tp.q_off[l] + (size_t)anc[l] * rows * S +
+                       (size_t)(anc[l - 1] % fan) * S;
+    double v[kPer];
+#pragma unroll
+    for (int t = 0; t < kPer; ++t) {
+      const int e = lane + 64 * t;
+      double acc = 0.0;
+      if (e < S * S) {
+        const int c = e / S, r = e % S;
+        for (int k = 0; k < S; ++k)
+          acc += qb[(size_t)k * rows + r] * out[c * S + k];
+      }
+      v[t] = acc;
+    }
+#pragma unroll
+    for (int t = 0; t < kPer; ++t) {
+      const int e = lane + 64 * t;
+      if (e < S * S) out[e] = v[t];
+    }
+  }
 }
 
 template <typename T, int S>
@@ -357,22 +432,61 @@ __global__ __launch_bounds__(256) void leaf_kernel(
   leaf_body<T, S>(v, ldv, m, nchunks, rleaf, blockIdx.x);
 }
 
+// The whole upward tree in one launch (after the leaves): each wave
+// factors one node of the first level, then counts itself in at the parent
+// node; the wave that completes a node's children invalidates its caches
+// at agent scope and factors that node, and goes on up, so the root is
+// done by the last wave to arrive.  Node R factors are written through to
+// the device level (st_r), so a wave's release is only the wait for its
+// stores.  The counters (ints at tp.cnt_off) start at zero and are put
+// back to zero by the wave that completes each node.
 template <int S>
-__global__ __launch_bounds__(256) void node_kernel(
-    const double* __restrict__ rprev, int64_t nprev, int fan, int64_t nnodes,
-    double* __restrict__ rcur, double* __restrict__ qcur, int is_root,
-    double* r_out, int64_t r_rs, int64_t r_cs, int32_t* syncs) {
+__global__ __launch_bounds__(256) void tree_kernel(
+    TsqrPlan tp, double* ws, double* r_out, int64_t r_rs, int64_t r_cs,
+    int32_t* syncs) {
   __shared__ double lds[4 * 4 * S * S];
-  node_body<S>(rprev, nprev, fan, nnodes, rcur, qcur, is_root, r_out, r_rs,
-               r_cs, syncs, lds, blockIdx.x);
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t node = (int64_t)blockIdx.x * 4 + wv;
+  if (node >= tp.nodes[1]) return;
+  double* my = lds + wv * 4 * S * S;
+  node_wave<S>(ws + tp.r_off[0], tp.nodes[0], tp.fan, node,
+               ws + tp.r_off[1], ws + tp.q_off[1], tp.levels == 1 ? 1 : 0,
+               r_out, r_rs, r_cs, syncs, my);
+  int* cnt = reinterpret_cast<int*>(ws + tp.cnt_off);
+  int64_t child = node, base = tp.nodes[1];
+  for (int l = 2; l <= tp.levels; ++l) {
+    const int64_t p = child / tp.fan;
+    const int nch = (int)min((int64_t)tp.fan, tp.nodes[l - 1] - p * tp.fan);
+    // this wave's node factor (written through) is complete
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    int old = 0;
+    if (lane == 0) old = atomicAdd(&cnt[base + p], 1);
+    old = __shfl(old, 0);
+    if (old + 1 != nch) return;             // a sibling completes p
+    if (lane == 0) cnt[base + p] = 0;
+    // the siblings' factors: drop any stale cached copies
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    node_wave<S>(ws + tp.r_off[l - 1], tp.nodes[l - 1], tp.fan, p,
+                 ws + tp.r_off[l], ws + tp.q_off[l], l == tp.levels ? 1 : 0,
+                 r_out, r_rs, r_cs, syncs, my);
+    base += tp.nodes[l];
+    child = p;
+  }
 }
 
+// Explicit Q of every chunk, each wave forming its chunk's coefficient
+// block from the tree's Q factors along its path (no downward launches).
 template <typename T, int S>
-__global__ __launch_bounds__(256) void apply_kernel(
-    const T* v, int64_t ldv, int64_t m, int64_t nchunks,
-    const double* __restrict__ cleaf, T* dst, int64_t ldd) {
-  __shared__ double lds[4 * 4 * S * S];
-  apply_body<T, S>(v, ldv, m, nchunks, cleaf, dst, ldd, lds, blockIdx.x);
+__global__ __launch_bounds__(256) void apply_path_kernel(
+    const T* v, int64_t ldv, int64_t m, TsqrPlan tp, const double* ws,
+    T* dst, int64_t ldd) {
+  __shared__ double lds[4 * 4 * S * S + 4 * S * S];
+  const int wv = threadIdx.x >> 6;
+  const int64_t chunk = (int64_t)blockIdx.x * 4 + wv;
+  if (chunk >= tp.nchunks) return;
+  double* c = lds + 4 * 4 * S * S + wv * S * S;
+  path_coef<S>(tp, ws, chunk, c);
+  apply_wave<T, S>(v, ldv, m, chunk, c, dst, ldd, lds + wv * 4 * S * S);
 }
 
 }  // namespace tw

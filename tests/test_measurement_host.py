@@ -89,5 +89,6 @@ def test_library_kernels_have_short_names():
                for n in names), sorted(names)[:20]
     assert "gram_reduce_kernel" in names
     assert "epilogue_kernel<16>" in names
-    assert "tsqr_wave_apply_kernel<double, 16>" in names
+    assert "tsqr_wave_apply_path_kernel<double, 16>" in names
+    assert "tsqr_wave_tree_kernel<16>" in names
     assert all("(" not in n and "::" not in n for n in names)
