@@ -71,11 +71,13 @@ __device__ __forceinline__ double bcast(double y, int lane) {
 // Wave sums of the P slots v[0..P-1].  On return slot c's total is held by
 // lane c << SH (and the other lanes of its group); read it with bcast().
 // Lane bits 5, 4, 3, 2 split the slots (the partner lane keeps the other
-// half of the slots); the remaining bits are summed over directly.
-template <int P>
+// half of the slots); the remaining bits are summed over directly.  With
+// HALVED the caller has already done the first split (v[i] = swap32_sum(
+// v[i], v[i + P/2]) for i < P/2), so fewer slots are live at once.
+template <int P, bool HALVED = false>
 __device__ __forceinline__ double wave_sums(double (&v)[P]) {
   const int lane = threadIdx.x & 63;
-  if constexpr (P >= 2) {
+  if constexpr (P >= 2 && !HALVED) {
 #pragma unroll
     for (int i = 0; i < P / 2; ++i) v[i] = swap32_sum(v[i], v[i + P / 2]);
   }
@@ -160,17 +162,24 @@ __device__ __forceinline__ void factor(double (&a)[Geo<S>::R][S],
       }
     }
     if constexpr (S > 1) {
+      // v^T a[:, c] for the slots c, each pair (c, c + P/2) combined by the
+      // first split of wave_sums as soon as both are formed
       double d[P];
 #pragma unroll
-      for (int c = 0; c < P; ++c) {
-        double acc = 0.0;
+      for (int c = 0; c < P / 2; ++c) {
+        double lo = 0.0, hi = 0.0;
+        const int c2 = c + P / 2;
         if (c < S && c != j && (c > j || z != nullptr)) {
 #pragma unroll
-          for (int k = 0; k < R; ++k) acc += v[k] * a[k][c];
+          for (int k = 0; k < R; ++k) lo += v[k] * a[k][c];
         }
-        d[c] = acc;
+        if (c2 < S && c2 != j && (c2 > j || z != nullptr)) {
+#pragma unroll
+          for (int k = 0; k < R; ++k) hi += v[k] * a[k][c2];
+        }
+        d[c] = swap32_sum(lo, hi);
       }
-      const double y = wave_sums<P>(d);
+      const double y = wave_sums<P, true>(d);
 #pragma unroll
       for (int c = j + 1; c < S; ++c) {
         const double tw = t * bcast(y, c << SH);
@@ -298,24 +307,25 @@ __device__ __forceinline__ void node_wave(
   double a[R][S], tau[S];
 #pragma unroll
   for (int k = 0; k < R; ++k) {
+    // row i of the stack: row rr of child ch (column c at c * S)
     const int i = lane + 64 * k;
     const int ch = i / S, rr = i % S;
+    const bool live = i < rows && ch < nch;
+    const double* src = rprev + (size_t)(c0 + (live ? ch : 0)) * S * S + rr;
 #pragma unroll
-    for (int c = 0; c < S; ++c)
-      a[k][c] = (i < rows && ch < nch)
-                    ? rprev[(size_t)(c0 + ch) * S * S + (size_t)c * S + rr]
-                    : 0.0;
+    for (int c = 0; c < S; ++c) a[k][c] = live ? src[c * S] : 0.0;
   }
   factor<S>(a, tau, my);
-  double sgn[S];
+  // columns whose sign the root flips (bit c), the same on every lane
+  unsigned neg = 0;
+  if (is_root) {
 #pragma unroll
-  for (int c = 0; c < S; ++c)
-    sgn[c] = (is_root && bcast(a[0][c], c) < 0.0) ? -1.0 : 1.0;
+    for (int c = 0; c < S; ++c)
+      if (bcast(a[0][c], c) < 0.0) neg |= 1u << c;
+  }
   if (lane < S) {
     double* rn = rcur + (size_t)node * S * S;
-    double mine = 1.0;                  // sign of this lane's row of R
-#pragma unroll
-    for (int c = 0; c < S; ++c) mine = c == lane ? sgn[c] : mine;
+    const double mine = (neg >> lane) & 1 ? -1.0 : 1.0;   // this lane's row
 #pragma unroll
     for (int c = 0; c < S; ++c) {
       const double val = (c >= lane ? a[0][c] : 0.0) * mine;
@@ -326,9 +336,7 @@ __device__ __forceinline__ void node_wave(
   double* qn = qcur + (size_t)node * rows * S;
   form_q<S>(a, nullptr, my, [&](int k, int c, double q) {
     const int i = lane + 64 * k;
-    double d = 1.0;
-#pragma unroll
-    for (int cc = 0; cc < S; ++cc) d = cc == c ? sgn[cc] : d;
+    const double d = (neg >> c) & 1 ? -1.0 : 1.0;
     if (i < rows) qn[(size_t)c * rows + i] = q * d;
   });
 }
@@ -390,12 +398,12 @@ __device__ __forceinline__ void path_coef(const TsqrPlan& tp,
                                           double* out) {
   const int lane = threadIdx.x & 63;
   const int L = tp.levels, fan = tp.fan, rows = fan * S;
-  int64_t anc[24];
-  anc[0] = chunk;
-  for (int l = 1; l <= L; ++l) anc[l] = anc[l - 1] / fan;
+  // ancestor of the chunk at level l: chunk / fan^l (wave-uniform)
+  int64_t span = 1;                         // fan^(L - 1)
+  for (int l = 1; l < L; ++l) span *= fan;
   constexpr int kPer = (S * S + 63) / 64;
   {
-    const double* qb = ws + tp.q_off[L] + (size_t)(anc[L - 1] % fan) * S;
+    const double* qb = ws + tp.q_off[L] + (size_t)((chunk / span) % fan) * S;
 #pragma unroll
     for (int t = 0; t < kPer; ++t) {
       const int e = lane + 64 * t;
@@ -403,8 +411,10 @@ __device__ __forceinline__ void path_coef(const TsqrPlan& tp,
     }
   }
   for (int l = L - 1; l >= 1; --l) {
-    const double* qb = ws + tp.q_off[l] + (size_t)anc[l] * rows * S +
-                       (size_t)(anc[l - 1] % fan) * S;
+    const int64_t below = span / fan;       // fan^(l - 1)
+    const double* qb = ws + tp.q_off[l] + (size_t)(chunk / span) * rows * S +
+                       (size_t)((chunk / below) % fan) * S;
+    span = below;
     double v[kPer];
 #pragma unroll
     for (int t = 0; t < kPer; ++t) {
