@@ -179,16 +179,31 @@ __device__ void gram_mfma(const EpiArgs& a, int js, int ca, int cb, int s,
 #pragma unroll
   for (int i = 0; i < kT; ++i) acc[i] = v4d{0.0, 0.0, 0.0, 0.0};
   const int nsteps = (js + 3) >> 2;
-  for (int t = 0; t < nsteps; ++t) {
-    const int r = 4 * t + lk;
+  // the operand loads of kG steps are issued before their MFMAs (the
+  // accumulation order is that of one step after the other)
+  constexpr int kG = 4;
+  for (int t0 = 0; t0 < nsteps; t0 += kG) {
+    double xs[kG][kT], ys[kG][kT];
 #pragma unroll
-    for (int i = 0; i < kT; ++i) {
-      const int id = wave + kWaves * i;
-      if (id < ntile) {
+    for (int u = 0; u < kG; ++u) {
+      const int r = 4 * (t0 + u) + lk;
+#pragma unroll
+      for (int i = 0; i < kT; ++i) {
+        const int id = wave + kWaves * i;
         const int bx = id / nb, by = id % nb;
-        const double x = r < js ? gram_at(a, r, ca + 16 * bx + li) : 0.0;
-        const double y = r < js ? gram_at(a, r, cb + 16 * by + li) : 0.0;
-        acc[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(x, y, acc[i], 0, 0, 0);
+        const bool live = id < ntile && r < js;
+        xs[u][i] = live ? gram_at(a, r, ca + 16 * bx + li) : 0.0;
+        ys[u][i] = live ? gram_at(a, r, cb + 16 * by + li) : 0.0;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kG; ++u) {
+      if (t0 + u >= nsteps) break;                    // wave-uniform
+#pragma unroll
+      for (int i = 0; i < kT; ++i) {
+        if (wave + kWaves * i < ntile)
+          acc[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(xs[u][i], ys[u][i],
+                                                        acc[i], 0, 0, 0);
       }
     }
   }
@@ -256,24 +271,40 @@ __device__ __forceinline__ void load_p(const EpiView& sm, const double* M,
 // in LDS (scr: 4 x 3 x 256 doubles).  Thread e < S*S receives entry
 // (e / S, e % S) of each block.
 template <int S>
-__device__ void gram_products(const EpiArgs& a, int js, bool has_e,
-                              double* scr, double& yy, double& yz,
-                              double& zz) {
+__device__ __forceinline__ void gram_products(const EpiArgs& a, int js,
+                                              bool has_e, double* scr,
+                                              double& yy, double& yz,
+                                              double& zz) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int li = lane & 15, lk = lane >> 4;
   const int w = has_e ? 2 * S : S;
   v4d b00 = {0.0, 0.0, 0.0, 0.0}, b01 = b00, b11 = b00;
   const int nsteps = (js + 3) / 4;
-  // column li of the first 16-column block; for S = 16 also of the second
+  // column li of the first 16-column block; for S = 16 also of the second.
+  // This wave's steps t = wave, wave + kWaves, ...: the Gram loads of kG of
+  // them are issued before their MFMAs (the accumulation order is that of
+  // one step after the other).
   const int c0 = li, c1 = 16 + li;
-  for (int t = wave; t < nsteps; t += kWaves) {
-    const int r = 4 * t + lk;
-    const double x0 = (r < js && c0 < w) ? gram_at(a, r, c0) : 0.0;
-    b00 = __builtin_amdgcn_mfma_f64_16x16x4f64(x0, x0, b00, 0, 0, 0);
-    if (S == 16 && has_e) {
-      const double x1 = r < js ? gram_at(a, r, c1) : 0.0;
-      b01 = __builtin_amdgcn_mfma_f64_16x16x4f64(x0, x1, b01, 0, 0, 0);
-      b11 = __builtin_amdgcn_mfma_f64_16x16x4f64(x1, x1, b11, 0, 0, 0);
+  constexpr int kG = 8;
+  const bool two = S == 16 && has_e;
+  for (int t0 = wave; t0 < nsteps; t0 += kG * kWaves) {
+    double x0[kG], x1[kG];
+#pragma unroll
+    for (int u = 0; u < kG; ++u) {
+      const int r = 4 * (t0 + kWaves * u) + lk;
+      x0[u] = (r < js && c0 < w) ? gram_at(a, r, c0) : 0.0;
+      x1[u] = (two && r < js) ? gram_at(a, r, c1) : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < kG; ++u) {
+      if (t0 + kWaves * u >= nsteps) break;           // wave-uniform
+      b00 = __builtin_amdgcn_mfma_f64_16x16x4f64(x0[u], x0[u], b00, 0, 0, 0);
+      if (two) {
+        b01 = __builtin_amdgcn_mfma_f64_16x16x4f64(x0[u], x1[u], b01, 0, 0,
+                                                   0);
+        b11 = __builtin_amdgcn_mfma_f64_16x16x4f64(x1[u], x1[u], b11, 0, 0,
+                                                   0);
+      }
     }
   }
   double* mine = scr + wave * 3 * 256;
@@ -317,7 +348,8 @@ __device__ void gram_products(const EpiArgs& a, int js, bool has_e,
 //   F2'(js+S:js+2S) = T2^{-1}
 // where T2 = S_{j+1,j+1} (scaled) or I, Z = Gram columns [S, 2S).
 template <int S>
-__device__ void coefs_fused(const EpiView& sm, const EpiArgs& a, int js) {
+__device__ __forceinline__ void coefs_fused(const EpiView& sm,
+                                            const EpiArgs& a, int js) {
   const int tid = threadIdx.x;
   const bool two = a.f2_mode != COEF_NONE;
   const bool scaled2 = a.f2_mode == COEF_SCALED;
@@ -385,14 +417,15 @@ __device__ void coefs_fused(const EpiView& sm, const EpiArgs& a, int js) {
   }
 }
 
-__device__ void store_identity(double* dst, int sp, int s) {
+__device__ __forceinline__ void store_identity(double* dst, int sp, int s) {
   for (int e = threadIdx.x; e < sp * sp; e += kThreads) {
     const int i = e / sp, l = e % sp;
     dst[e] = (i == l && i < s) ? 1.0 : 0.0;
   }
 }
 
-__device__ void store_tri(double* dst, int sp, int s, const double* src) {
+__device__ __forceinline__ void store_tri(double* dst, int sp, int s,
+                                          const double* src) {
   for (int e = threadIdx.x; e < sp * sp; e += kThreads) {
     const int i = e / sp, l = e % sp;
     dst[e] = (i < s && l < s) ? src[i * s + l] : 0.0;
@@ -404,9 +437,11 @@ __device__ void store_tri(double* dst, int sp, int s, const double* src) {
 // C1 / C2 per thread: the row is loaded whole into registers (S > 0: the
 // block width is a compile-time constant and the loops unroll).
 template <int S>
-__device__ void assemble_r(const EpiView& sm, const EpiArgs& a, const double* c1,
-                           const double* c2, const double* T1,
-                           const double* t2, bool c1_is_gram = false) {
+__device__ __forceinline__ void assemble_r(const EpiView& sm,
+                                           const EpiArgs& a, const double* c1,
+                                           const double* c2, const double* T1,
+                                           const double* t2,
+                                           bool c1_is_gram = false) {
   const int s = S ? S : a.s, sp = a.sp, js = a.j * s;
   double* T2 = sm.B;
   __syncthreads();
@@ -416,16 +451,46 @@ __device__ void assemble_r(const EpiView& sm, const EpiArgs& a, const double* c1
   if constexpr (S == 4 || S == 8 || S == 16) {
     load_p<S>(sm, T2, S);
     __syncthreads();
-    mm16<S>(
-        js,
-        [&](int i, int k) {
-          return c1_is_gram ? gram_at(a, i, k) : c1[(size_t)i * sp + k];
-        },
-        sm.P,
-        [&](int i, int c, double v) {
-          if (c < S)
-            a.r[(size_t)(js + c) * a.ldr + i] = v + c2[(size_t)i * sp + c];
-        });
+    // R(i, js + c) = C2(i, c) + sum_k C1(i, k) T2(k, c) on the 16x16x4 MFMA
+    // (as mm16), row blocks of 16 dealt to the waves; the C1 and C2 loads
+    // of kG of a wave's row blocks are issued before their MFMAs
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int li = lane & 15, lk = lane >> 4;
+    constexpr int kG = 4;
+    for (int rb0 = wave; rb0 * 16 < js; rb0 += kG * kWaves) {
+      double av[kG][S / 4], cv[kG][4];
+#pragma unroll
+      for (int g = 0; g < kG; ++g) {
+        const int rb = rb0 + kWaves * g;
+        const int i = rb * 16 + li;
+#pragma unroll
+        for (int q = 0; q < S / 4; ++q)
+          av[g][q] = i < js ? (c1_is_gram ? gram_at(a, i, 4 * q + lk)
+                                          : c1[(size_t)i * sp + 4 * q + lk])
+                            : 0.0;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int r = rb * 16 + lk + 4 * v;
+          cv[g][v] = (r < js && li < S) ? c2[(size_t)r * sp + li] : 0.0;
+        }
+      }
+#pragma unroll
+      for (int g = 0; g < kG; ++g) {
+        const int rb = rb0 + kWaves * g;
+        if (rb * 16 >= js) break;                     // wave-uniform
+        v4d acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int q = 0; q < S / 4; ++q)
+          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(
+              av[g][q], sm.P[(4 * q + lk) * 16 + li], acc, 0, 0, 0);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int r = rb * 16 + lk + 4 * v;
+          if (r < js && li < S)
+            a.r[(size_t)(js + li) * a.ldr + r] = acc[v] + cv[g][v];
+        }
+      }
+    }
   } else
   for (int i = threadIdx.x; i < js; i += kThreads) {
     double y[S ? S : kMaxS];
@@ -459,8 +524,10 @@ __device__ void assemble_r(const EpiView& sm, const EpiArgs& a, const double* c1
 // F = [-C T^{-1}; T^{-1}] (scaled) or [-C; I] (unscaled), C with K rows.
 // T^{-1} by back substitution, one column per thread, in FP64.
 template <int S>
-__device__ void make_coef(const EpiView& sm, double* F, const double* C, int K,
-                          const double* T, int scaled, int s_, int sp) {
+__device__ __forceinline__ void make_coef(const EpiView& sm, double* F,
+                                          const double* C, int K,
+                                          const double* T, int scaled, int s_,
+                                          int sp) {
   const int tid = threadIdx.x, s = S ? S : s_;
   double* Ti = sm.B;                  // s x s row-major
   double* Tl = sm.A;                  // LDS copy of T (s x s row-major)
@@ -534,7 +601,8 @@ __device__ void make_coef(const EpiView& sm, double* F, const double* C, int K,
 //   F2'(0 : K1+s) = [F2(0 : K1); 0] + F1 F2(K1 : K1+s),
 // the same product in exact arithmetic.  One row of F1 per thread.
 template <int S>
-__device__ void fold_coefs(const EpiView& sm, const EpiArgs& a) {
+__device__ __forceinline__ void fold_coefs(const EpiView& sm,
+                                           const EpiArgs& a) {
   const int s = S ? S : a.s, sp = a.sp, K1 = a.f1_rows;
   double* M = sm.A;                   // F2(K1 : K1+s), s x s row-major
   if constexpr (S == 4 || S == 8 || S == 16) {
@@ -573,7 +641,8 @@ __device__ void fold_coefs(const EpiView& sm, const EpiArgs& a) {
 }
 
 template <int S>
-__device__ void make_coefs(const EpiView& sm, const EpiArgs& a) {
+__device__ __forceinline__ void make_coefs(const EpiView& sm,
+                                           const EpiArgs& a) {
   __syncthreads();
   if (a.f1_mode != COEF_NONE)
     make_coef<S>(sm, a.f1, a.c1, a.f1_rows, a.t1, a.f1_mode == COEF_SCALED,
@@ -586,7 +655,8 @@ __device__ void make_coefs(const EpiView& sm, const EpiArgs& a) {
 }
 
 template <int S>
-__device__ bool epilogue_body(EpiArgs a, const EpiView& sm);
+__device__ __forceinline__ bool epilogue_body(EpiArgs a,
+                                              const EpiView& sm);
 
 // The whole epilogue on the LDS arrays of `sm` (one workgroup)
 template <int S>
@@ -603,7 +673,8 @@ __global__ __launch_bounds__(kThreads) void epilogue_kernel(EpiArgs a) {
 
 // Returns true when it has also written the coefficient matrices.
 template <int S>
-__device__ bool epilogue_body(EpiArgs a, const EpiView& sm) {
+__device__ __forceinline__ bool epilogue_body(EpiArgs a,
+                                              const EpiView& sm) {
   constexpr bool kFast = S == 4 || S == 8 || S == 16;
   const int tid = threadIdx.x;
   const int s = S ? S : a.s, sp = a.sp, js = a.j * s;
