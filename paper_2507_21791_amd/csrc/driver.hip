@@ -76,6 +76,9 @@ bool make_plan(int64_t m, int64_t n, int64_t s, int variant, int precision,
   P.off_partial = off;
   off = align256(off + (size_t)P.G * P.partial_elems * sizeof(double));
   P.off_tsqr = off; off = align256(off + P.tsqr.total * sizeof(double));
+  P.off_fsplit = off;
+  if (P.sp == 32)
+    off = align256(off + 2 * (size_t)(n + s) * 16 * sizeof(double));
   P.bytes = off;
   *p = P;
   return true;
@@ -130,6 +133,111 @@ struct Run {
     bool scaled2 = true;               // update 2 has a triangular factor
   };
 
+  // The block updates of a pass without a Gram at s = 32 (g: the pass as
+  // the generic kernel would run it) on the s <= 16 pass, whose two
+  // updates of 16 columns each become the two halves of one 32-column
+  // block: the second half's K range takes in the first half's staged
+  // (old) columns, and the pass forms both products before writing either.
+  // Update 2 runs first (its block is not among update 1's staged
+  // columns), then update 1, which rewrites its own block in place; both
+  // read the old columns, as the folded coefficients assume.  The caller
+  // has put the first update's coefficient halves in the split buffer and
+  // opened a launch record; each launch gets a record of its own with its
+  // own byte and flop model.  Returns hipErrorNotSupported, with nothing
+  // launched, where the s <= 16 pass does not take the shape; the generic
+  // pass then runs.
+  hipError_t split_updates(const Pass& d, const PassArgs<T>& g, int* tag) {
+    if constexpr (sizeof(T) != 8) {
+      return hipErrorNotSupported;
+    } else {
+      const int s = p.s;
+      double* fa = dws(p.off_fsplit);
+      double* fb = fa + (size_t)(p.n + s) * 16;
+      const double mr = (double)p.m;
+      // one 32-column block [c0, c0 + 32) into dst, from the first nq
+      // staged Q columns (and block F with with_f), on the open record
+      auto half = [&](int nq, bool with_f, int c0, T* dst) -> hipError_t {
+        PassArgs<T> h = g;
+        h.s = 16; h.sp = 16;
+        h.nq = nq;
+        h.fcols = with_f ? s : 0;
+        h.e = nullptr; h.ecols = 0;
+        h.ncols = nq + h.fcols;
+        h.ncols_p = round_up(h.ncols, 16);
+        h.upd1 = 1; h.u1_c0 = c0; h.c1 = fa; h.dst1 = dst; h.ldd1 = ldq;
+        h.upd2 = 1; h.u2_c0 = c0 + 16; h.c2 = fb;
+        h.dst2 = dst + (int64_t)16 * ldq; h.ldd2 = ldq;
+        h.gram = 0; h.groups = 1;
+        prof_model(8.0 * mr * (h.ncols + s),
+                   mr * (2.0 * c0 * s + (double)s * s));
+        int g16 = 0;
+        return launch_pass16(h, p.m, p.tune, st, tag, &g16);
+      };
+      if (d.upd2) {
+        const hipError_t e = half(d.nq, true, d.nq, d.dst2);
+        if (e != hipSuccess || !d.upd1) return e;
+        // close update 2's record; update 1's halves replace update 2's
+        // in the split buffer (ordered after update 2's launch on the
+        // stream), then update 1 on a record of its own
+        prof_end();
+        prof_retag(*tag);
+        check(launch_split_coef(g.c1, g.u1_c0 + s, p.sp, fa, fb, st));
+        prof_begin(BCGS_KERNEL_PASS, -1, 0.0, 0.0);
+      }
+      return half(d.nq, false, d.nq - s, Q + (int64_t)(d.nq - s) * ldq);
+    }
+  }
+
+  // The Gram of a pass without updates at s = 32 as one launch of the
+  // s <= 16 pass per 32 B columns (its two 16-column B blocks), each
+  // followed by its reduction into its columns of the reduced Gram (only
+  // the last one counts as the synchronization point).  False, with
+  // nothing launched, where the s <= 16 pass does not take the shape.
+  bool gram_halves(const Pass& d) {
+    if constexpr (sizeof(T) != 8) {
+      return false;
+    } else {
+      const int s = p.s;
+      PassArgs<T> h{};
+      h.m = p.m; h.s = 16; h.sp = 16;
+      h.q = Q; h.ldq = ldq; h.nq = d.nq;
+      h.f = d.f; h.ldf = d.ldf; h.fcols = d.f ? s : 0;
+      h.e = d.e; h.lde = d.lde; h.ecols = d.e ? s : 0;
+      h.ncols = h.nq + h.fcols + h.ecols;
+      h.ncols_p = round_up(h.ncols, 16);
+      h.gram = 1; h.groups = 1;
+      h.ga_p = h.ncols_p;
+      h.gbn_p = 32;
+      h.partial = dws(p.off_partial);
+      const int nh = d.gbn > 32 ? 2 : 1;
+      const double mr = (double)p.m;
+      for (int k = 0; k < nh; ++k) {
+        h.gb0 = d.gb0 + 32 * k;
+        // the E^T U tiles the method does not need lie in the first half
+        h.skip_a0 = d.skip_eu ? d.nq + s : 1 << 30;
+        h.skip_b1 = d.skip_eu && k == 0 ? s : 0;
+        int tag = 0, g16 = 0;
+        prof_begin(BCGS_KERNEL_PASS, -1, 8.0 * mr * h.ncols,
+                   2.0 * mr * (double)d.needed / nh);
+        const hipError_t e = launch_pass16(h, p.m, p.tune, st, &tag, &g16);
+        if (e == hipErrorNotSupported && k == 0) {
+          // nothing launched: close the record on an empty launch
+          prof_model(0.0, 0.0);
+          prof_end();
+          return false;
+        }
+        check(e);
+        prof_end();
+        prof_retag(tag);
+        check(launch_gram_reduce(h.partial, g16, (int64_t)h.ga_p * 32,
+                                 dws(p.off_gram) + (size_t)k * h.ga_p * 32,
+                                 k == nh - 1 ? &info->syncs : nullptr, st));
+      }
+      gram_ld_last = h.ga_p;
+      return true;
+    }
+  }
+
   void pass(const Pass& d) {
     const int s = p.s;
     PassArgs<T> a{};
@@ -159,6 +267,21 @@ struct Run {
     const int ta_total = a.ga_p / 16;
     int groups = 1;
     if (d.gram) groups = (int)cdiv(ta_total, kWaves * maxa);
+    if (sizeof(T) == 8 && p.sp == 32 && s == 32 && d.gram && !rec_active()) {
+      // s = 32: the updates on their own (split_updates), then the Gram in
+      // halves of 32 B columns on the s <= 16 pass (gram_halves)
+      Pass gdesc = d;
+      if (d.upd1 || d.upd2) {
+        Pass u = d;
+        u.gram = false;
+        pass(u);
+        gdesc.upd1 = false;
+        gdesc.upd2 = false;
+        if (d.upd2) { gdesc.f = d.dst2; gdesc.ldf = ldq; }
+      }
+      if (gram_halves(gdesc)) return;
+      if (d.upd1 || d.upd2) { pass(gdesc); return; }
+    }
     if (groups > 1 && (d.upd1 || d.upd2)) {
       // the Gram is split over several workgroups per row range: run the
       // updates on their own first, then the Gram reading their results
@@ -196,8 +319,20 @@ struct Run {
     }
     if (d.gram) flops += 2.0 * mr * (double)d.needed;
     int tag = 0;
+    // s = 32 block updates without a Gram: the halves of each block's
+    // coefficients in the s <= 16 pass's layout (see split_updates)
+    const bool split = sizeof(T) == 8 && p.sp == 32 && s == 32 && !d.gram &&
+                       (d.upd1 || d.upd2) && !rec_active();
+    if (split) {
+      double* fa = dws(p.off_fsplit);
+      double* fb = fa + (size_t)(p.n + s) * 16;
+      const double* F = d.upd2 ? a.c2 : a.c1;
+      const int K = d.upd2 ? a.u2_c0 + s : a.u1_c0 + s;
+      check(launch_split_coef(F, K, p.sp, fa, fb, st));
+    }
     prof_begin(BCGS_KERNEL_PASS, -1, esz * mr * cols_rw, flops);
     hipError_t e = hipErrorNotSupported;
+    if (split) e = split_updates(d, a, &tag);
     if (p.sp == 16) {
       int g16 = 0;
       if constexpr (sizeof(T) == 8)

@@ -88,7 +88,7 @@ __device__ __forceinline__ double lane_bcast(double v, int lane) {
   return __hiloint2double(hi, lo);
 }
 
-// The same factorization by wave 0 alone for a compile-time s <= 16: lane
+// The same factorization by wave 0 alone for a compile-time s <= 32: lane
 // l holds column l in registers, the pivot and the row of R are broadcast
 // with readlane, so no step needs a barrier.  Same breakdown rule, same
 // record in bcgs_info, same NaN fill.
@@ -135,7 +135,7 @@ __device__ void chol_wave(const EpiView& sm, bcgs_info* info, int block,
 template <int S>
 __device__ __forceinline__ void chol(const EpiView& sm, int s, bcgs_info* info,
                                      int block, int stage) {
-  if constexpr (S > 0 && S <= 16) chol_wave<S>(sm, info, block, stage);
+  if constexpr (S > 0 && S <= 32) chol_wave<S>(sm, info, block, stage);
   else chol_lds(sm, s, info, block, stage);
 }
 

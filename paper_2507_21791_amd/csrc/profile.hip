@@ -59,6 +59,14 @@ void prof_begin(int kind, int tag, double bytes, double flops) {
   p->recs.push_back(r);
 }
 
+void prof_model(double bytes, double flops) {
+  Prof* p = t_cur;
+  if (p && !p->recs.empty()) {
+    p->recs.back().bytes = bytes;
+    p->recs.back().flops = flops;
+  }
+}
+
 void prof_retag(int tag) {
   Prof* p = t_cur;
   if (p && !p->recs.empty()) p->recs.back().tag = tag;
