@@ -130,8 +130,9 @@ struct Plan {
   // workspace offsets in bytes
   size_t off_c1, off_c2, off_t1, off_t2, off_f1, off_f2, off_gram,
       off_partial, off_tsqr;
-  size_t off_fsplit;      // s = 32: two (n + s) x 16 halves of a coefficient
-                          // matrix (the block updates on the s <= 16 pass)
+  size_t off_fsplit;      // s = 32, 64: two (n + s) x 16 column blocks of a
+                          // coefficient matrix (block updates on the s <= 16
+                          // pass)
   size_t off_scratch_info;
   size_t bytes;
   int64_t gram_ld;        // leading dimension of the reduced Gram matrix
@@ -209,10 +210,10 @@ hipError_t launch_tsqr(const TsqrPlan& tp, const T* v, int64_t ldv, T* dst,
 
 hipError_t launch_fill(double* p, int64_t rows, int64_t cols, int64_t ld,
                        double value, hipStream_t st);
-// Columns [0, 16) and [16, 32) of the K x sp row-major matrix F (sp >= 32)
-// as two K x 16 row-major matrices fa and fb.
-hipError_t launch_split_coef(const double* F, int64_t K, int sp, double* fa,
-                             double* fb, hipStream_t st);
+// Columns [c0, c0 + 16) and [c0 + 16, c0 + 32) of the K x sp row-major
+// matrix F (c0 + 32 <= sp) as two K x 16 row-major matrices fa and fb.
+hipError_t launch_split_coef(const double* F, int64_t K, int sp, int c0,
+                             double* fa, double* fb, hipStream_t st);
 
 // --------------------------------------------------------- epilogues ---
 enum EpiMode : int {

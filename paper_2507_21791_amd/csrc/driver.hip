@@ -77,7 +77,7 @@ bool make_plan(int64_t m, int64_t n, int64_t s, int variant, int precision,
   off = align256(off + (size_t)P.G * P.partial_elems * sizeof(double));
   P.off_tsqr = off; off = align256(off + P.tsqr.total * sizeof(double));
   P.off_fsplit = off;
-  if (P.sp == 32)
+  if (s == 32 || s == 64)
     off = align256(off + 2 * (size_t)(n + s) * 16 * sizeof(double));
   P.bytes = off;
   *p = P;
@@ -133,19 +133,21 @@ struct Run {
     bool scaled2 = true;               // update 2 has a triangular factor
   };
 
-  // The block updates of a pass without a Gram at s = 32 (g: the pass as
-  // the generic kernel would run it) on the s <= 16 pass, whose two
-  // updates of 16 columns each become the two halves of one 32-column
-  // block: the second half's K range takes in the first half's staged
+  // The block updates of a pass without a Gram at s = 32 or 64 (g: the
+  // pass as the generic kernel would run it) on the s <= 16 pass, whose two
+  // updates of 16 columns each become two neighbouring 16-column parts of a
+  // block: the second part's K range takes in the first part's staged
   // (old) columns, and the pass forms both products before writing either.
-  // Update 2 runs first (its block is not among update 1's staged
-  // columns), then update 1, which rewrites its own block in place; both
-  // read the old columns, as the folded coefficients assume.  The caller
-  // has put the first update's coefficient halves in the split buffer and
-  // opened a launch record; each launch gets a record of its own with its
-  // own byte and flop model.  Returns hipErrorNotSupported, with nothing
-  // launched, where the s <= 16 pass does not take the shape; the generic
-  // pass then runs.
+  // A block of 64 columns takes two launches, its last 32 columns first: a
+  // launch writes only columns that no later launch reads, so every launch
+  // reads old columns, as the folded coefficients assume.  Update 2 runs
+  // first (its block is not among update 1's staged columns), then update
+  // 1, which rewrites its own block in place.  The caller has put the
+  // coefficient parts of the first launch in the split buffer and opened a
+  // launch record; each launch gets a record of its own with its own byte
+  // and flop model.  Returns hipErrorNotSupported, with nothing launched,
+  // where the s <= 16 pass does not take the shape; the generic pass then
+  // runs.
   hipError_t split_updates(const Pass& d, const PassArgs<T>& g, int* tag) {
     if constexpr (sizeof(T) != 8) {
       return hipErrorNotSupported;
@@ -154,37 +156,54 @@ struct Run {
       double* fa = dws(p.off_fsplit);
       double* fb = fa + (size_t)(p.n + s) * 16;
       const double mr = (double)p.m;
-      // one 32-column block [c0, c0 + 32) into dst, from the first nq
-      // staged Q columns (and block F with with_f), on the open record
-      auto half = [&](int nq, bool with_f, int c0, T* dst) -> hipError_t {
+      // columns [c0, c0 + 32) of the block at staged column b0 (into dst),
+      // staging the columns up to the part's end: Q columns, then with
+      // with_f the first columns of block F (the block is F at b0 = nq)
+      auto part = [&](int nq, bool with_f, int b0, int c0,
+                      T* dst) -> hipError_t {
         PassArgs<T> h = g;
         h.s = 16; h.sp = 16;
-        h.nq = nq;
-        h.fcols = with_f ? s : 0;
+        h.nq = with_f ? nq : b0 + c0 + 32;
+        h.fcols = with_f ? c0 + 32 : 0;
         h.e = nullptr; h.ecols = 0;
-        h.ncols = nq + h.fcols;
+        h.ncols = h.nq + h.fcols;
         h.ncols_p = round_up(h.ncols, 16);
-        h.upd1 = 1; h.u1_c0 = c0; h.c1 = fa; h.dst1 = dst; h.ldd1 = ldq;
-        h.upd2 = 1; h.u2_c0 = c0 + 16; h.c2 = fb;
-        h.dst2 = dst + (int64_t)16 * ldq; h.ldd2 = ldq;
+        h.upd1 = 1; h.u1_c0 = b0 + c0; h.c1 = fa;
+        h.dst1 = dst + (int64_t)c0 * ldq; h.ldd1 = ldq;
+        h.upd2 = 1; h.u2_c0 = b0 + c0 + 16; h.c2 = fb;
+        h.dst2 = dst + (int64_t)(c0 + 16) * ldq; h.ldd2 = ldq;
         h.gram = 0; h.groups = 1;
-        prof_model(8.0 * mr * (h.ncols + s),
-                   mr * (2.0 * c0 * s + (double)s * s));
+        prof_model(8.0 * mr * (h.ncols + 32),
+                   mr * (2.0 * (b0 + c0) * 32 + 32.0 * 32));
         int g16 = 0;
         return launch_pass16(h, p.m, p.tune, st, tag, &g16);
       };
-      if (d.upd2) {
-        const hipError_t e = half(d.nq, true, d.nq, d.dst2);
-        if (e != hipSuccess || !d.upd1) return e;
-        // close update 2's record; update 1's halves replace update 2's
-        // in the split buffer (ordered after update 2's launch on the
-        // stream), then update 1 on a record of its own
-        prof_end();
-        prof_retag(*tag);
-        check(launch_split_coef(g.c1, g.u1_c0 + s, p.sp, fa, fb, st));
-        prof_begin(BCGS_KERNEL_PASS, -1, 0.0, 0.0);
+      struct Job { bool with_f; int b0; const double* F; T* dst; };
+      Job jobs[2];
+      int nj = 0;
+      if (d.upd2) jobs[nj++] = {true, d.nq, g.c2, d.dst2};
+      if (d.upd1)
+        jobs[nj++] = {false, d.nq - s, g.c1, Q + (int64_t)(d.nq - s) * ldq};
+      bool first = true;
+      for (int j = 0; j < nj; ++j) {
+        const Job& jb = jobs[j];
+        for (int c0 = s - 32; c0 >= 0; c0 -= 32) {
+          if (!first) {
+            // close the last launch's record; this launch's coefficient
+            // parts replace the last ones in the split buffer (ordered after
+            // that launch on the stream); then a record of its own
+            prof_end();
+            prof_retag(*tag);
+            check(launch_split_coef(jb.F, jb.b0 + c0 + 32, p.sp, c0, fa, fb,
+                                    st));
+            prof_begin(BCGS_KERNEL_PASS, -1, 0.0, 0.0);
+          }
+          const hipError_t e = part(d.nq, jb.with_f, jb.b0, c0, jb.dst);
+          if (e != hipSuccess) return e;
+          first = false;
+        }
       }
-      return half(d.nq, false, d.nq - s, Q + (int64_t)(d.nq - s) * ldq);
+      return hipSuccess;
     }
   }
 
@@ -319,16 +338,17 @@ struct Run {
     }
     if (d.gram) flops += 2.0 * mr * (double)d.needed;
     int tag = 0;
-    // s = 32 block updates without a Gram: the halves of each block's
-    // coefficients in the s <= 16 pass's layout (see split_updates)
-    const bool split = sizeof(T) == 8 && p.sp == 32 && s == 32 && !d.gram &&
+    // s = 32, 64 block updates without a Gram on the s <= 16 pass (see
+    // split_updates)
+    const bool split = sizeof(T) == 8 && (s == 32 || s == 64) && !d.gram &&
                        (d.upd1 || d.upd2) && !rec_active();
     if (split) {
+      // the first launch's parts: the last 32 columns of the first update
       double* fa = dws(p.off_fsplit);
       double* fb = fa + (size_t)(p.n + s) * 16;
       const double* F = d.upd2 ? a.c2 : a.c1;
       const int K = d.upd2 ? a.u2_c0 + s : a.u1_c0 + s;
-      check(launch_split_coef(F, K, p.sp, fa, fb, st));
+      check(launch_split_coef(F, K, p.sp, s - 32, fa, fb, st));
     }
     prof_begin(BCGS_KERNEL_PASS, -1, esz * mr * cols_rw, flops);
     hipError_t e = hipErrorNotSupported;

@@ -66,22 +66,22 @@ hipError_t launch_fill(double* p, int64_t rows, int64_t cols, int64_t ld,
 }
 
 __global__ void split_coef_kernel(const double* __restrict__ F, int64_t K,
-                                  int sp, double* __restrict__ fa,
+                                  int sp, int c0, double* __restrict__ fa,
                                   double* __restrict__ fb) {
   const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (e >= K * 16) return;
   const int64_t k = e >> 4;
   const int c = (int)(e & 15);
-  fa[e] = F[k * sp + c];
-  fb[e] = F[k * sp + 16 + c];
+  fa[e] = F[k * sp + c0 + c];
+  fb[e] = F[k * sp + c0 + 16 + c];
 }
 
-hipError_t launch_split_coef(const double* F, int64_t K, int sp, double* fa,
-                             double* fb, hipStream_t st) {
+hipError_t launch_split_coef(const double* F, int64_t K, int sp, int c0,
+                             double* fa, double* fb, hipStream_t st) {
   if (K <= 0) return hipSuccess;
   prof_begin(BCGS_KERNEL_OTHER, 1, 8.0 * K * 32 * 2, 0.0);
   hipLaunchKernelGGL(split_coef_kernel, dim3((unsigned)cdiv(K * 16, 256)),
-                     dim3(256), 0, st, F, K, sp, fa, fb);
+                     dim3(256), 0, st, F, K, sp, c0, fa, fb);
   prof_name("split_coef_kernel");
   prof_end();
   return hipGetLastError();
