@@ -658,6 +658,30 @@ template <int S>
 __device__ __forceinline__ bool epilogue_body(EpiArgs a,
                                               const EpiView& sm);
 
+// dst(i, c) = G(i, col0 + c) for c < s, 0 for s <= c < sp (rows i < rows,
+// row-major with stride sp): the Gram loads of eight elements per thread
+// are issued before their stores.
+__device__ __forceinline__ void copy_gram_rows(const EpiArgs& a, double* dst,
+                                               int rows, int col0, int s,
+                                               int sp) {
+  constexpr int kB = 8;
+  const int total = rows * sp;
+  for (int base = threadIdx.x; base < total; base += kB * kThreads) {
+    double v[kB];
+#pragma unroll
+    for (int u = 0; u < kB; ++u) {
+      const int e = min(base + u * kThreads, total - 1);
+      const int i = e / sp, c = e % sp;
+      v[u] = c < s ? gram_at(a, i, col0 + c) : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < kB; ++u) {
+      const int e = base + u * kThreads;
+      if (e < total) dst[e] = v[u];
+    }
+  }
+}
+
 // The whole epilogue on the LDS arrays of `sm` (one workgroup)
 template <int S>
 __device__ __forceinline__ void epilogue_all(const EpiArgs& a,
@@ -681,10 +705,7 @@ __device__ __forceinline__ bool epilogue_body(EpiArgs a,
 
   if (a.mode == EPI_S_ONLY || a.mode == EPI_Y_ONLY) {
     double* dst = a.mode == EPI_S_ONLY ? a.c2 : a.c1;
-    for (int e = tid; e < js * sp; e += kThreads) {
-      const int i = e / sp, c = e % sp;
-      dst[e] = c < s ? gram_at(a, i, c) : 0.0;
-    }
+    copy_gram_rows(a, dst, js, 0, s, sp);
     if (a.unit_s) store_identity(a.t2, sp, s);
     return false;
   }
@@ -699,10 +720,7 @@ __device__ __forceinline__ bool epilogue_body(EpiArgs a,
   if (a.mode == EPI_S_CHOL) {
     // gram rows [0, js) = S_{1:j,j+1}, rows [js, js+s) = T_{j+1}
     // (columns [0, s)); S_{j+1,j+1} = chol(T - S^T S)
-    for (int e = tid; e < js * sp; e += kThreads) {
-      const int i = e / sp, c = e % sp;
-      a.c2[e] = c < s ? gram_at(a, i, c) : 0.0;
-    }
+    copy_gram_rows(a, a.c2, js, 0, s, sp);
     if constexpr (S == 4 || S == 8 || S == 16) {
       double ss = 0.0, unused1 = 0.0, unused2 = 0.0;
       gram_products<S>(a, js, false, sm.B, ss, unused1, unused2);
@@ -794,10 +812,7 @@ __device__ __forceinline__ bool epilogue_body(EpiArgs a,
   if constexpr (kFast) {
     if (tid < S * S) sm.T1[tid] = sm.A[tid];
   } else {
-    for (int e = tid; e < js * sp; e += kThreads) {
-      const int i = e / sp, c = e % sp;
-      a.c1[e] = c < s ? gram_at(a, i, c) : 0.0;
-    }
+    copy_gram_rows(a, a.c1, js, 0, s, sp);
   }
   store_tri(a.t1, sp, s, sm.A);
   __syncthreads();
@@ -844,11 +859,10 @@ __device__ __forceinline__ bool epilogue_body(EpiArgs a,
     if (tid < S * S) sm.L[tid] = sm.B[tid];
   }
   // C2 <- [Z; L]
-  for (int e = tid; e < (js + s) * sp; e += kThreads) {
+  copy_gram_rows(a, a.c2, js, s, s, sp);
+  for (int e = tid; e < s * sp; e += kThreads) {
     const int i = e / sp, c = e % sp;
-    double v = 0.0;
-    if (c < s) v = i < js ? gram_at(a, i, s + c) : sm.B[(i - js) * s + c];
-    a.c2[e] = v;
+    a.c2[(size_t)(js + i) * sp + c] = c < s ? sm.B[i * s + c] : 0.0;
   }
   if (a.unit_s) {                     // BCGSI+1s: S_{j+1,j+1} = I
     store_identity(a.t2, sp, s);
