@@ -221,6 +221,54 @@ __device__ void gram_mfma(const EpiArgs& a, int js, int ca, int cb, int s,
   __syncthreads();
 }
 
+// Y^T Y, Y^T Z and Z^T Z over the js Gram rows for s = 32 (Y = Gram columns
+// [0, 32), Z = [32, 64); only Y^T Y without Z) in one sweep: each wave owns
+// the same 16 x 16 tile (bx, by) of the three products and runs one MFMA
+// chain per product over all rows, the tile sequence of gram_mfma (so the
+// same sums), with the Gram loads of kG steps issued before their MFMAs.
+// out: the three products row-major, 32 x 32 each, one after another.
+__device__ __forceinline__ void gram_three32(const EpiArgs& a, int js,
+                                             bool has_e, double* out) {
+  constexpr int s = 32, kG = 8;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int bx = wave >> 1, by = wave & 1;
+  v4d yy = {0.0, 0.0, 0.0, 0.0}, yz = yy, zz = yy;
+  const int nsteps = (js + 3) >> 2;
+  for (int t0 = 0; t0 < nsteps; t0 += kG) {
+    double yb[kG], yc[kG], zb[kG], zc[kG];
+#pragma unroll
+    for (int u = 0; u < kG; ++u) {
+      const int r = 4 * (t0 + u) + lk;
+      const bool live = r < js;
+      yb[u] = live ? gram_at(a, r, 16 * bx + li) : 0.0;
+      yc[u] = live ? gram_at(a, r, 16 * by + li) : 0.0;
+      zb[u] = live && has_e ? gram_at(a, r, s + 16 * bx + li) : 0.0;
+      zc[u] = live && has_e ? gram_at(a, r, s + 16 * by + li) : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < kG; ++u) {
+      if (t0 + u >= nsteps) break;                    // wave-uniform
+      yy = __builtin_amdgcn_mfma_f64_16x16x4f64(yb[u], yc[u], yy, 0, 0, 0);
+      if (has_e) {
+        yz = __builtin_amdgcn_mfma_f64_16x16x4f64(yb[u], zc[u], yz, 0, 0, 0);
+        zz = __builtin_amdgcn_mfma_f64_16x16x4f64(zb[u], zc[u], zz, 0, 0, 0);
+      }
+    }
+  }
+  // acc[v] at lane l: row 16 bx + l / 16 + 4 v, column 16 by + l % 16
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int e = (16 * bx + lk + 4 * v) * s + 16 * by + li;
+    out[e] = yy[v];
+    if (has_e) {
+      out[s * s + e] = yz[v];
+      out[2 * s * s + e] = zz[v];
+    }
+  }
+  __syncthreads();
+}
+
 // Tall-by-small products on the FP64 16x16x4 MFMA, for block widths
 // S = 4, 8, 16: out(i, c, v) receives v = sum_{k < S} A(i, k) P(k, c) for
 // i < rows and c < 16, with P a 16 x 16 row-major LDS matrix that is zero
@@ -757,6 +805,21 @@ __device__ __forceinline__ bool epilogue_body(EpiArgs a,
   for (int t = 0; t < kPer; ++t) yy[t] = yz[t] = zz[t] = 0.0;
   if constexpr (S == 4 || S == 8 || S == 16) {
     gram_products<S>(a, js, a.has_e, sm.B, yy[0], yz[0], zz[0]);
+  } else if (S == 32) {
+    // the three products in one sweep, through sm.A
+    gram_three32(a, js, a.has_e, sm.A);
+#pragma unroll
+    for (int t = 0; t < kPer; ++t) {
+      const int e = tid + t * kThreads;
+      if (e < s * s) {
+        yy[t] = sm.A[e];
+        if (a.has_e) {
+          yz[t] = sm.A[s * s + e];
+          zz[t] = sm.A[2 * s * s + e];
+        }
+      }
+    }
+    __syncthreads();
   } else if (s % 16 == 0) {
     // the three products one after another through sm.A
     for (int p = 0; p < (a.has_e ? 3 : 1); ++p) {
