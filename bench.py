@@ -336,16 +336,21 @@ def bench_twin(steps, warmup):
     return out
 
 
-def bench_sweep(steps, warmup, sizes=(4, 8, 16, 32, 64)):
+def bench_sweep(steps, warmup, sizes=(4, 8, 16, 32, 64), ld_pad=16):
     """The block-size sweep (m = 2^20, n = 512, kappa about 1.05, seed 3):
     time, algorithmic GB/s and TFLOP/s of P-1S, P-2S and BCGSI+ for each
-    block size s."""
+    block size s, with X and Q stored with leading dimension m + ld_pad as
+    in the headline run."""
     import torch
     from paper_2507_21791_amd import bcgs, workloads as W
     w = W.WORKLOADS["sweep"]
-    X = W.make_device("sweep")
-    Q = bcgs.empty_fortran(w["m"], w["n"], torch.float64, "cuda")
-    R = bcgs.empty_fortran(w["n"], w["n"], torch.float64, "cuda")
+    m, n = w["m"], w["n"]
+    X0 = W.make_device("sweep")
+    X = bcgs.empty_fortran(m, n, torch.float64, "cuda", ld=m + ld_pad)
+    X.copy_(X0)
+    del X0
+    Q = bcgs.empty_fortran(m, n, torch.float64, "cuda", ld=m + ld_pad)
+    R = bcgs.empty_fortran(n, n, torch.float64, "cuda")
     rows = []
     for s in sizes:
         row = {"s": s}
@@ -362,8 +367,9 @@ def bench_sweep(steps, warmup, sizes=(4, 8, 16, 32, 64)):
         rows.append(row)
     del X, Q, R
     torch.cuda.empty_cache()
-    return {"workload": (f"sweep: m={w['m']} n={w['n']} kappa~1.05 FP64, "
-                         f"{steps} timed steps each"), "rows": rows}
+    return {"workload": (f"sweep: m={m} n={n} kappa~1.05 FP64, leading "
+                         f"dimension m + {ld_pad}, {steps} timed steps each"),
+            "rows": rows}
 
 
 def _time_batched(batch, reps, mode):
@@ -828,7 +834,7 @@ def main():
     if not args.no_twin:
         out["tall_k6"] = bench_twin(args.steps, args.warmup)
     if not args.no_sweep:
-        out["sweep"] = bench_sweep(args.sweep_steps, 1)
+        out["sweep"] = bench_sweep(args.sweep_steps, 1, ld_pad=args.ld_pad)
     if not args.no_batched:
         out["batched"] = bench_batched(args.batched_count, 3)
     if not args.no_served:
