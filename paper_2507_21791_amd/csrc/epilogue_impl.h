@@ -539,6 +539,21 @@ __device__ __forceinline__ void assemble_r(const EpiView& sm,
         }
       }
     }
+  } else if constexpr (S == 32) {
+    // R(i, js + c) = C2(i, c) + sum_k C1(i, k) T2(k, c), one 16-column
+    // block of T2 at a time, on the 16x16x4 MFMA
+    for (int cb = 0; cb < 2; ++cb) {
+      for (int e = threadIdx.x; e < 512; e += kThreads)
+        sm.P2[e] = T2[(e >> 4) * 32 + 16 * cb + (e & 15)];
+      __syncthreads();
+      mm16<32>(
+          js, [&](int i, int k) { return c1[(size_t)i * sp + k]; }, sm.P2,
+          [&](int i, int c, double v) {
+            a.r[(size_t)(js + 16 * cb + c) * a.ldr + i] =
+                v + c2[(size_t)i * sp + 16 * cb + c];
+          });
+      __syncthreads();
+    }
   } else
   for (int i = threadIdx.x; i < js; i += kThreads) {
     double y[S ? S : kMaxS];
@@ -583,7 +598,7 @@ __device__ __forceinline__ void make_coef(const EpiView& sm, double* F,
     for (int e = tid; e < s * s; e += kThreads)
       Tl[e] = T[(e / s) * sp + e % s];
     __syncthreads();
-    if constexpr (S > 0 && S <= 16) {
+    if constexpr (S > 0 && S <= 32) {
       tri_inv_wave<S>(Tl, Ti);
     } else if (tid < s) {
       const int j = tid;
@@ -609,6 +624,19 @@ __device__ __forceinline__ void make_coef(const EpiView& sm, double* F,
     mm16<S>(
         K, [&](int i, int k) { return C[(size_t)i * sp + k]; }, sm.P,
         [&](int i, int c, double v) { F[(size_t)i * sp + c] = -v; });
+  } else if constexpr (S == 32) {
+    // F(0:K, :) = -C T^{-1}, one 16-column block of T^{-1} at a time
+    for (int cb = 0; cb < 2; ++cb) {
+      for (int e = tid; e < 512; e += kThreads)
+        sm.P2[e] = Ti[(e >> 4) * 32 + 16 * cb + (e & 15)];
+      __syncthreads();
+      mm16<32>(
+          K, [&](int i, int k) { return C[(size_t)i * sp + k]; }, sm.P2,
+          [&](int i, int c, double v) {
+            F[(size_t)i * sp + 16 * cb + c] = -v;
+          });
+      __syncthreads();
+    }
   } else
   // one row of C per thread: F(i, :) = -C(i, :) T^{-1}  (or -C(i, :))
   for (int i = tid; i < K; i += kThreads) {
@@ -668,6 +696,22 @@ __device__ __forceinline__ void fold_coefs(const EpiView& sm,
   for (int e = threadIdx.x; e < s * s; e += kThreads)
     M[e] = a.f2[(size_t)(K1 + e / s) * sp + e % s];
   __syncthreads();
+  if constexpr (S == 32) {
+    // one 16-column block of M at a time, on the 16x16x4 MFMA
+    for (int cb = 0; cb < 2; ++cb) {
+      for (int e = threadIdx.x; e < 512; e += kThreads)
+        sm.P2[e] = M[(e >> 4) * 32 + 16 * cb + (e & 15)];
+      __syncthreads();
+      mm16<32>(
+          K1 + s, [&](int i, int k) { return a.f1[(size_t)i * sp + k]; },
+          sm.P2, [&](int i, int c, double v) {
+            double* o = a.f2 + (size_t)i * sp + 16 * cb + c;
+            *o = (i < K1 ? *o : 0.0) + v;
+          });
+      __syncthreads();
+    }
+    return;
+  }
   for (int i = threadIdx.x; i < K1 + s; i += kThreads) {
     double fr[S ? S : kMaxS];
 #pragma unroll
