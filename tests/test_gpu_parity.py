@@ -82,16 +82,18 @@ def test_sweep_reduced_rows(variant, s):
     compare(X, s, variant, host(Qg), host(Rg), info)
 
 
+@pytest.mark.parametrize("n,s", [(64, 16), (128, 32), (192, 64)])
 @pytest.mark.parametrize("variant", VARIANTS5)
-def test_exact_case_bitwise(variant):
+def test_exact_case_bitwise(variant, n, s):
     """Scaled permuted identity: every step is exact, so the GPU must return
     R = diag(2^e) and Q = X diag(2^-e) bit for bit (same closed form the
-    oracle reproduces exactly)."""
-    log(f"[gpu] exact scaled permuted identity {variant}")
-    n = 64
+    oracle reproduces exactly).  At s = 32 and 64 this covers the passes
+    split into 16-column parts and the epilogue's MFMA products: a
+    coefficient in the wrong place breaks the exact result."""
+    log(f"[gpu] exact scaled permuted identity n={n} s={s} {variant}")
     e = np.random.default_rng(3).integers(-20, 20, size=n)
     X = W.scaled_permuted_identity(3000, n, e, seed=3)
-    Qg, Rg, info = run_gpu(X, 16, variant)
+    Qg, Rg, info = run_gpu(X, s, variant)
     assert info.status == 0
     assert np.array_equal(host(Rg), np.diag(np.ldexp(1.0, e)))
     assert np.array_equal(host(Qg), X * np.ldexp(1.0, -e)[None, :])
