@@ -301,6 +301,39 @@ __device__ __forceinline__ void mm16(int rows, FA a_at, const double* P,
   }
 }
 
+// mm16 with a run-time K (a multiple of 4, at most kMaxS): out(i, c, v)
+// receives sum_{k < K} A(i, k) P(k, c) for i < rows and c < 16, P a K x 16
+// row-major LDS matrix; the loads of eight K-steps are issued before their
+// MFMAs.
+template <class FA, class FO>
+__device__ __forceinline__ void mm16_rt(int rows, int K, FA a_at,
+                                        const double* P, FO out) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int nq = K >> 2;
+  for (int rb = wave; rb * 16 < rows; rb += kWaves) {
+    const int i = rb * 16 + li;
+    v4d acc = {0.0, 0.0, 0.0, 0.0};
+    for (int q0 = 0; q0 < nq; q0 += 8) {
+      double av[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        av[u] = (i < rows && q0 + u < nq) ? a_at(i, 4 * (q0 + u) + lk) : 0.0;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        if (q0 + u >= nq) break;                      // wave-uniform
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(
+            av[u], P[(4 * (q0 + u) + lk) * 16 + li], acc, 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int r = rb * 16 + lk + 4 * v;
+      if (r < rows) out(r, li, acc[v]);
+    }
+  }
+}
+
 // P <- the S x S row-major matrix M (leading dimension ldm), zero-padded
 // to 16 x 16
 template <int S>
@@ -624,6 +657,20 @@ __device__ __forceinline__ void make_coef(const EpiView& sm, double* F,
     mm16<S>(
         K, [&](int i, int k) { return C[(size_t)i * sp + k]; }, sm.P,
         [&](int i, int c, double v) { F[(size_t)i * sp + c] = -v; });
+  } else if (S == 0 && s % 16 == 0) {
+    // run-time s (48, 64): F(0:K, :) = -C T^{-1} on the MFMA, one 16-column
+    // block of T^{-1} at a time staged in sm.A (free after the inverse)
+    for (int cb = 0; cb < s / 16; ++cb) {
+      for (int e = tid; e < s * 16; e += kThreads)
+        sm.A[e] = Ti[(e >> 4) * s + 16 * cb + (e & 15)];
+      __syncthreads();
+      mm16_rt(
+          K, s, [&](int i, int k) { return C[(size_t)i * sp + k]; }, sm.A,
+          [&](int i, int c, double v) {
+            F[(size_t)i * sp + 16 * cb + c] = -v;
+          });
+      __syncthreads();
+    }
   } else if constexpr (S == 32) {
     // F(0:K, :) = -C T^{-1}, one 16-column block of T^{-1} at a time
     for (int cb = 0; cb < 2; ++cb) {
@@ -696,6 +743,23 @@ __device__ __forceinline__ void fold_coefs(const EpiView& sm,
   for (int e = threadIdx.x; e < s * s; e += kThreads)
     M[e] = a.f2[(size_t)(K1 + e / s) * sp + e % s];
   __syncthreads();
+  if (S == 0 && s % 16 == 0) {
+    // run-time s (48, 64): one 16-column block of M at a time, staged in
+    // sm.B, on the 16x16x4 MFMA
+    for (int cb = 0; cb < s / 16; ++cb) {
+      for (int e = threadIdx.x; e < s * 16; e += kThreads)
+        sm.B[e] = M[(e >> 4) * s + 16 * cb + (e & 15)];
+      __syncthreads();
+      mm16_rt(
+          K1 + s, s, [&](int i, int k) { return a.f1[(size_t)i * sp + k]; },
+          sm.B, [&](int i, int c, double v) {
+            double* o = a.f2 + (size_t)i * sp + 16 * cb + c;
+            *o = (i < K1 ? *o : 0.0) + v;
+          });
+      __syncthreads();
+    }
+    return;
+  }
   if constexpr (S == 32) {
     // one 16-column block of M at a time, on the 16x16x4 MFMA
     for (int cb = 0; cb < 2; ++cb) {
