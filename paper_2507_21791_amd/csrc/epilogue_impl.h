@@ -88,7 +88,7 @@ __device__ __forceinline__ double lane_bcast(double v, int lane) {
   return __hiloint2double(hi, lo);
 }
 
-// The same factorization by wave 0 alone for a compile-time s <= 32: lane
+// The same factorization by wave 0 alone for s <= 32 and s = 64: lane
 // l holds column l in registers, the pivot and the row of R are broadcast
 // with readlane, so no step needs a barrier.  Same breakdown rule, same
 // record in bcgs_info, same NaN fill.
@@ -135,8 +135,14 @@ __device__ void chol_wave(const EpiView& sm, bcgs_info* info, int block,
 template <int S>
 __device__ __forceinline__ void chol(const EpiView& sm, int s, bcgs_info* info,
                                      int block, int stage) {
-  if constexpr (S > 0 && S <= 32) chol_wave<S>(sm, info, block, stage);
-  else chol_lds(sm, s, info, block, stage);
+  if constexpr (S > 0 && S <= 32) {
+    chol_wave<S>(sm, info, block, stage);
+  } else if constexpr (S == 0) {
+    if (s == 64) chol_wave<64>(sm, info, block, stage);
+    else chol_lds(sm, s, info, block, stage);
+  } else {
+    chol_lds(sm, s, info, block, stage);
+  }
 }
 
 // T^{-1} of the upper triangular s x s matrix T (row-major, LDS) into Ti:
@@ -587,6 +593,26 @@ __device__ __forceinline__ void assemble_r(const EpiView& sm,
           });
       __syncthreads();
     }
+  } else if (S == 0 && s % 16 == 0) {
+    // run-time s (48, 64): R(i, js + c) = C2(i, c) + sum_k C1(i, k) T2(k, c)
+    // on the MFMA, per 16-column block of T2 and K range of 32 rows (the
+    // 32 x 16 operand in sm.P2), the later K ranges added to R
+    for (int cb = 0; cb < s / 16; ++cb) {
+      for (int k0 = 0; k0 < s; k0 += 32) {
+        const int kc = min(32, s - k0);
+        for (int e = threadIdx.x; e < kc * 16; e += kThreads)
+          sm.P2[e] = T2[(k0 + (e >> 4)) * s + 16 * cb + (e & 15)];
+        __syncthreads();
+        mm16_rt(
+            js, kc,
+            [&](int i, int k) { return c1[(size_t)i * sp + k0 + k]; }, sm.P2,
+            [&](int i, int c, double v) {
+              double* o = a.r + (size_t)(js + 16 * cb + c) * a.ldr + i;
+              *o = (k0 == 0 ? c2[(size_t)i * sp + 16 * cb + c] : *o) + v;
+            });
+        __syncthreads();
+      }
+    }
   } else
   for (int i = threadIdx.x; i < js; i += kThreads) {
     double y[S ? S : kMaxS];
@@ -657,6 +683,19 @@ __device__ __forceinline__ void make_coef(const EpiView& sm, double* F,
     mm16<S>(
         K, [&](int i, int k) { return C[(size_t)i * sp + k]; }, sm.P,
         [&](int i, int c, double v) { F[(size_t)i * sp + c] = -v; });
+  } else if constexpr (S == 32) {
+    // F(0:K, :) = -C T^{-1}, one 16-column block of T^{-1} at a time
+    for (int cb = 0; cb < 2; ++cb) {
+      for (int e = tid; e < 512; e += kThreads)
+        sm.P2[e] = Ti[(e >> 4) * 32 + 16 * cb + (e & 15)];
+      __syncthreads();
+      mm16<32>(
+          K, [&](int i, int k) { return C[(size_t)i * sp + k]; }, sm.P2,
+          [&](int i, int c, double v) {
+            F[(size_t)i * sp + 16 * cb + c] = -v;
+          });
+      __syncthreads();
+    }
   } else if (S == 0 && s % 16 == 0) {
     // run-time s (48, 64): F(0:K, :) = -C T^{-1} on the MFMA, one 16-column
     // block of T^{-1} at a time staged in sm.A (free after the inverse)
@@ -666,19 +705,6 @@ __device__ __forceinline__ void make_coef(const EpiView& sm, double* F,
       __syncthreads();
       mm16_rt(
           K, s, [&](int i, int k) { return C[(size_t)i * sp + k]; }, sm.A,
-          [&](int i, int c, double v) {
-            F[(size_t)i * sp + 16 * cb + c] = -v;
-          });
-      __syncthreads();
-    }
-  } else if constexpr (S == 32) {
-    // F(0:K, :) = -C T^{-1}, one 16-column block of T^{-1} at a time
-    for (int cb = 0; cb < 2; ++cb) {
-      for (int e = tid; e < 512; e += kThreads)
-        sm.P2[e] = Ti[(e >> 4) * 32 + 16 * cb + (e & 15)];
-      __syncthreads();
-      mm16<32>(
-          K, [&](int i, int k) { return C[(size_t)i * sp + k]; }, sm.P2,
           [&](int i, int c, double v) {
             F[(size_t)i * sp + 16 * cb + c] = -v;
           });
